@@ -1,0 +1,75 @@
+"""The guiding MLP in float64 (oracle).
+
+Test infrastructure only. Sec. 4.1: fully connected layers without bias and
+ReLU between them; the input is padded with a constant one, which stands in
+for the bias (footnote of Sec. 4.1). Here the input is the 9 raw features
+(position, outgoing direction, normal) followed by that one: 10 values.
+
+Weights are a list of matrices W_l of shape [out_l, in_l]; layer l computes
+h_l = relu(W_l h_{l-1}) and the last layer is linear.
+"""
+
+import torch
+
+F64 = torch.float64
+IN_FEATURES = 9
+
+
+def layer_shapes(hidden, n_hidden, n_lobes):
+    """[(out, in)] for n_hidden hidden layers of width `hidden` and 8K outputs."""
+    shapes = [(hidden, IN_FEATURES + 1)]
+    shapes += [(hidden, hidden)] * (n_hidden - 1)
+    shapes.append((8 * n_lobes, hidden))
+    return shapes
+
+
+def unflatten(flat, shapes):
+    """Flat row-major concatenation of W_0 .. W_L -> list of matrices."""
+    flat = torch.as_tensor(flat, dtype=F64)
+    out, off = [], 0
+    for (o, i) in shapes:
+        out.append(flat[off:off + o * i].reshape(o, i))
+        off += o * i
+    assert off == flat.numel()
+    return out
+
+
+def flatten(mats):
+    return torch.cat([m.reshape(-1) for m in mats])
+
+
+def round_bf16(t):
+    """Round to the nearest bfloat16 (ties to even) through float32.
+
+    In the autograd graph the rounding is the identity (straight-through), so
+    gradients are those of the network with the rounded values.
+    """
+    r = t.detach().to(torch.float32).to(torch.bfloat16).to(F64)
+    return t + (r - t.detach())
+
+
+def forward(weights, feat, bf16=False, return_pre=False):
+    """Raw outputs [B, 8K] for features [B, 9].
+
+    bf16=True emulates a BF16 GEMM with wide accumulation: every weight and
+    every layer input (the features and the constant one included) is rounded
+    to bfloat16, products are summed in float64, and a hidden pre-activation
+    is rounded to float32 before the ReLU and the next rounding to bfloat16.
+    The last layer's result is not rounded.
+    """
+    feat = torch.as_tensor(feat, dtype=F64)
+    h = torch.cat([feat, torch.ones(feat.shape[0], 1, dtype=F64)], dim=-1)
+    pre = []
+    n = len(weights)
+    for l, W in enumerate(weights):
+        W = torch.as_tensor(W, dtype=F64)
+        if bf16:
+            W = round_bf16(W)
+            h = round_bf16(h)
+        y = h @ W.T
+        pre.append(y)
+        if l < n - 1:
+            if bf16:
+                y = y + (y.detach().to(torch.float32).to(F64) - y.detach())
+            h = torch.relu(y)
+    return (y, pre) if return_pre else y

@@ -1,0 +1,60 @@
+"""Training objective and optimiser in float64 (oracle).
+
+Test infrastructure only.
+
+Sec. 4.2: the gradient of KL(p || q) is estimated from one sample per vertex
+as -E[(p / q_hat) grad log q]. With w = p / q_hat supplied per training sample
+(the MIS-weighted radiance over the sampling pdf, Sec. 5), that is the
+gradient of the weighted negative log-likelihood
+    L = (1/B) sum_j w_j * (-log q(dir_j | feat_j)),
+which is what this module computes (reading: mean over the batch). Its
+gradient is taken by float64 autograd of the literal forward; Adam follows
+Kingma and Ba (the optimiser the paper uses with Libtorch, Sec. 5).
+"""
+
+import torch
+
+from . import mlp, nasg
+
+F64 = torch.float64
+
+
+def weighted_nll(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False):
+    """L = mean_j w_j * (-log q(dir_j)) for one batch (scalar tensor)."""
+    raw = mlp.forward(weights, feat, bf16=bf16)
+    lobes = nasg.decode(raw, n_lobes, eps)
+    log_q = nasg.mixture_log_pdf(dirs, lobes)
+    w = torch.as_tensor(w, dtype=F64)
+    return (w * (-log_q)).mean()
+
+
+def loss_and_grad(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False):
+    """(L, [dL/dW_l]) with the gradient from float64 autograd."""
+    ws = [torch.as_tensor(W, dtype=F64).clone().requires_grad_(True) for W in weights]
+    L = weighted_nll(ws, feat, dirs, w, n_lobes, eps, bf16)
+    grads = torch.autograd.grad(L, ws)
+    return float(L.detach()), [g.detach() for g in grads]
+
+
+def raw_output_grad(raw, dirs, w, n_lobes, eps=0.0):
+    """dL/d(raw outputs) [B, 8K] for the loss above, by autograd."""
+    raw = torch.as_tensor(raw, dtype=F64).clone().requires_grad_(True)
+    log_q = nasg.mixture_log_pdf(dirs, nasg.decode(raw, n_lobes, eps))
+    w = torch.as_tensor(w, dtype=F64)
+    L = (w * (-log_q)).mean()
+    (g,) = torch.autograd.grad(L, raw)
+    return g.detach()
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1), bias-corrected, no decay.
+
+    `step` is the number of updates already taken; returns
+    (param, m, v, step + 1) as new tensors.
+    """
+    t = step + 1
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return param - lr * m_hat / (torch.sqrt(v_hat) + eps), m, v, t
