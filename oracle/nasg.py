@@ -43,13 +43,15 @@ def _unit_pair(c, s):
     """Divide a (cos, sin) pair by its norm; a zero pair becomes (1, 0).
 
     Reading: the decoded sine/cosine values of Tab. "decoding" are independent
-    sigmoids, so they are projected onto the unit circle before use.
+    sigmoids, so they are projected onto the unit circle before use. The zero
+    pair is replaced before the norm is taken, so its derivative is zero
+    rather than undefined.
     """
-    n = torch.sqrt(c * c + s * s)
-    ok = n > 0
-    n_safe = torch.where(ok, n, torch.ones_like(n))
-    return (torch.where(ok, c / n_safe, torch.ones_like(c)),
-            torch.where(ok, s / n_safe, torch.zeros_like(s)))
+    ok = (c * c + s * s) > 0
+    c1 = torch.where(ok, c, torch.ones_like(c))
+    s1 = torch.where(ok, s, torch.zeros_like(s))
+    n = torch.sqrt(c1 * c1 + s1 * s1)
+    return c1 / n, s1 / n
 
 
 def log_normaliser(lam, a, eps=0.0):

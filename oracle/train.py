@@ -46,6 +46,15 @@ def raw_output_grad(raw, dirs, w, n_lobes, eps=0.0):
     return g.detach()
 
 
+def weight_grad_from_raw_grad(weights, feat, g_raw, bf16=False):
+    """[dL/dW_l] given dL/d(raw outputs): the MLP part of the chain rule, by
+    autograd of sum(raw * g_raw) with g_raw held fixed."""
+    ws = [torch.as_tensor(W, dtype=F64).clone().requires_grad_(True) for W in weights]
+    raw = mlp.forward(ws, feat, bf16=bf16)
+    s = (raw * torch.as_tensor(g_raw, dtype=F64)).sum()
+    return [g.detach() for g in torch.autograd.grad(s, ws)]
+
+
 def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma and Ba, Algorithm 1), bias-corrected, no decay.
 

@@ -442,3 +442,19 @@ def test_raw_output_grad_matches_finite_differences():
             rm = raw.clone(); rm[i, j] -= 1e-6
             fd[i, j] = (loss(rp) - loss(rm)) / 2e-6
     assert float(torch.abs(fd - g).max()) < 1e-7
+
+
+def test_weight_grad_from_raw_grad_is_the_chain_rule():
+    """Composing raw_output_grad with the MLP backward reproduces the full
+    weight gradient (same network, same data)."""
+    rng = np.random.default_rng(16)
+    K = 2
+    Ws = [torch.tensor(rng.uniform(-0.5, 0.5, s)) for s in mlp.layer_shapes(8, 3, K)]
+    feat = torch.tensor(rng.standard_normal((20, 9)))
+    d = rng.standard_normal((20, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    w = torch.tensor(np.exp(rng.standard_normal(20)))
+    _, full = train.loss_and_grad(Ws, feat, torch.tensor(d), w, K)
+    g_raw = train.raw_output_grad(mlp.forward(Ws, feat), torch.tensor(d), w, K)
+    staged = train.weight_grad_from_raw_grad(Ws, feat, g_raw)
+    for a, b in zip(full, staged):
+        assert torch.allclose(a, b, rtol=1e-12, atol=1e-14)
