@@ -1,0 +1,322 @@
+"""Benchmark: the online guiding frame loop on one MI355X.
+
+One step = one frame of a 1-spp path tracer's guiding work: NASG queries
+(MLP forward + decode + sample + pdf) for 2^20, 600000, 300000 and 120000
+vertices (four bounces), then one training step (fused forward recompute +
+weighted-NLL backward + Adam) on 2^18 samples, with the BF16 network
+9 -> 64 x 4 -> 8*16 (K = 16 NASG lobes). Inputs are synthetic, seeded and
+resident in HBM before timing. The frame is captured once as a HIP graph and
+replayed. Prints one JSON line.
+
+Also measured: the same frame with the FP32 network, the stand-alone
+nasg_pdf / nasg_sample kernels on stored records (2^20 vertices), the query
+kernel's roofline (HIP events around repeated launches), and the FP64
+oracle on the host CPU for a bounded sample of the frame.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NASG queries/s (fwd+sample+pdf) & train samples/s (fwd+bwd), bf16 vs fp32"
+BOUNCES = (1 << 20, 600000, 300000, 120000)
+TRAIN_B = 1 << 18
+H, NH, K = 64, 4, 16
+
+# MI355X published peaks used for the roofline fractions
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP32 op per
+# lane per cycle; transcendentals take four such slots)
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def query_valu_ops(k):
+    """Algorithmic VALU op-slots of one query with k lobes (cost model:
+    add/mul/fma/compare/select = 1 slot, exp2/log2/rcp/rsqrt/sqrt/sin/cos = 4).
+    Per lobe 180: decode of five sin/cos values 50, sin theta 6, the two pair
+    normalisations 16, frame 7, lambda and a 14, log K 20, mixture weight 9,
+    lobe value at the sampled direction with its log-sum-exp term 55, CDF 3.
+    Per vertex 100: direct sampling 88, normalising the direction 8,
+    cross-lane reductions and stores 4."""
+    return 180 * k + 100
+
+
+def mlp_flops(hidden, n_hidden, k):
+    macs = hidden * 10 + (n_hidden - 1) * hidden * hidden + 8 * k * hidden
+    return 2 * macs
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-graph", action="store_true")
+    p.add_argument("--only", choices=["frame", "query", "records", "train"], default=None,
+                   help="run one leg only (for profilers)")
+    return p.parse_args()
+
+
+class Frame:
+    """Device-resident inputs and the launch sequence of one frame."""
+
+    def __init__(self, precision, seed=1000):
+        import torch
+        from paper_2303_08064_amd import synth
+        from paper_2303_08064_amd.nasg import NasgGuide
+        self.torch = torch
+        mats = synth.init_weights(synth.layer_shapes(H, NH, K), synth.rng_for(42))
+        self.guide = NasgGuide(synth.flat_weights(mats), hidden=H, n_hidden=NH, n_lobes=K,
+                               precision=precision, lr=1e-3, max_batch=TRAIN_B)
+        rng = synth.rng_for(seed)
+        dev = "cuda"
+        self.q_in = []
+        for n in BOUNCES:
+            self.q_in.append((torch.from_numpy(synth.features(n, rng)).to(dev),
+                              torch.from_numpy(synth.uniforms(n, rng)).to(dev)))
+        self.q_out = [(torch.empty(3, n, device=dev), torch.empty(n, device=dev)) for n in BOUNCES]
+        tgt = synth.VmfTarget(4, seed=1001)
+        f, d, w = synth.training_batch(TRAIN_B, rng, tgt)
+        self.t_in = (torch.from_numpy(f).to(dev), torch.from_numpy(d).to(dev), torch.from_numpy(w).to(dev))
+        torch.cuda.synchronize()
+
+    def run(self):
+        g = self.guide
+        for (f, xi), (d, p) in zip(self.q_in, self.q_out):
+            g.query(f, xi, dir_out=d, pdf_out=p)
+        g.train_step(*self.t_in)
+
+
+def time_frames(frame, steps, warmup, use_graph):
+    import torch
+    for _ in range(warmup):
+        frame.run()
+    torch.cuda.synchronize()
+    replay = frame.run
+    if use_graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            frame.run()   # one more eager pass on the capture stream
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=s):
+                frame.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        replay = graph.replay
+        for _ in range(2):
+            replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    return ms, wall
+
+
+def kernel_avg_ms(fn, reps):
+    """Average duration of fn's launches, by HIP events on the launching stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2303_08064_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+QUERY_SOURCES = ["query.hip", "mlp.hpp", "nasg_math.hpp", "common.hpp", "kernels.hpp", "layout.hpp"]
+
+
+def committed_traffic():
+    """HBM bytes per query launch from the committed counter summary, if it was
+    taken on the current query-kernel sources."""
+    p = os.path.join(ROOT, "profiles", "query_bf16_k16_1m_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash(QUERY_SOURCES):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def query_roofline(frame, reps=20):
+    import torch
+    g = frame.guide
+    (f, xi), (d, p) = frame.q_in[0], frame.q_out[0]
+    ms = kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p), reps)
+    n = f.shape[1]
+    ops = query_valu_ops(K) * n
+    achieved = ops / (ms * 1e-3) / 1e12
+    mfma = mlp_flops(H, NH, K) * n / (ms * 1e-3) / 1e12
+    hbm = (9 + 4 + 3 + 1) * 4 * n / (ms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    return {
+        "kernel": "query_kernel<64,16,bf16> (nasg_query, 2^20 vertices)",
+        "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
+        "unit": "TOP/s (VALU op-slots)", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+        "traffic": committed_traffic(), "avg_ms": round(ms, 4),
+        "mfma_tflops": round(mfma, 2), "mfma_frac_bf16": round(mfma / PEAK_BF16_TFLOPS, 4),
+        "hbm_gbs_algorithmic": round(hbm, 1),
+    }
+
+
+def records_legs(frame, reps=20):
+    import torch
+    from paper_2303_08064_amd import synth
+    from paper_2303_08064_amd.nasg import record_elems
+    g = frame.guide
+    (f, xi), (d, p) = frame.q_in[0], frame.q_out[0]
+    n = f.shape[1]
+    rec = torch.empty(record_elems(K, n), device="cuda")
+    g.query(f, xi, dir_out=d, pdf_out=p, rec_out=rec)
+    xi2 = torch.from_numpy(synth.uniforms(n, synth.rng_for(77))).cuda()
+    pdf_out = torch.empty(n, device="cuda")
+    d2, p2 = torch.empty(3, n, device="cuda"), torch.empty(n, device="cuda")
+    ms_pdf = kernel_avg_ms(lambda: g.pdf(rec, d, pdf_out=pdf_out), reps)
+    ms_smp = kernel_avg_ms(lambda: g.sample(rec, xi2, dir_out=d2, pdf_out=p2), reps)
+    rec_bytes = 9 * K * 4
+    b_pdf = (rec_bytes + 12 + 4) * n
+    b_smp = (rec_bytes + 16 + 12 + 4) * n
+    return {
+        "pdf": {"avg_ms": round(ms_pdf, 4), "gbs": round(b_pdf / (ms_pdf * 1e-3) / 1e9, 1),
+                "frac_hbm": round(b_pdf / (ms_pdf * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "sample": {"avg_ms": round(ms_smp, 4), "gbs": round(b_smp / (ms_smp * 1e-3) / 1e9, 1),
+                   "frac_hbm": round(b_smp / (ms_smp * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "vertices": n,
+    }
+
+
+def train_leg(frame, reps=10):
+    g = frame.guide
+    ms = kernel_avg_ms(lambda: g.train_step(*frame.t_in), reps)
+    return {"avg_ms": round(ms, 4), "samples_per_s": round(TRAIN_B / (ms * 1e-3), 1)}
+
+
+def cpu_baseline(fraction=4):
+    """The FP64 oracle on the host: 1/fraction of a frame's queries (each bounce
+    scaled) and training samples, timed; reported in queries/s of frames."""
+    import torch
+    from oracle import mlp as omlp, nasg as onasg, train as otrain
+    from paper_2303_08064_amd import synth
+    mats = synth.init_weights(synth.layer_shapes(H, NH, K), synth.rng_for(42))
+    W = [torch.tensor(m, dtype=torch.float64) for m in mats]
+    rng = synth.rng_for(2000)
+    nq = [n // fraction for n in BOUNCES]
+    nt = TRAIN_B // fraction
+    chunk = 65536
+    t0 = time.perf_counter()
+    for n in nq:
+        for s in range(0, n, chunk):
+            m = min(chunk, n - s)
+            f, xi = synth.features(m, rng), synth.uniforms(m, rng)
+            lob = onasg.decode(omlp.forward(W, f.T, bf16=True), K)
+            v, _ = onasg.sample(lob, xi.T.astype(np.float64))
+            onasg.mixture_log_pdf(v, lob)
+    tgt = synth.VmfTarget(4, seed=1001)
+    grads = None
+    for s in range(0, nt, chunk):
+        m = min(chunk, nt - s)
+        f, d, w = synth.training_batch(m, rng, tgt)
+        _, gl = otrain.loss_and_grad(W, f.T, d.T, w.astype(np.float64), K, bf16=True)
+        grads = gl if grads is None else [a + b for a, b in zip(grads, gl)]
+    flat = torch.cat([x.reshape(-1) for x in grads])
+    z = torch.zeros_like(flat)
+    otrain.adam_step(torch.cat([x.reshape(-1) for x in W]), flat, z, z.clone(), 0, 1e-3)
+    dt = time.perf_counter() - t0
+    frames_per_s = (1.0 / fraction) / dt
+    return {"value": round(frames_per_s * sum(BOUNCES), 1), "unit": "queries/s", "cores": torch.get_num_threads(),
+            "kind": "oracle", "seconds": round(dt, 2),
+            "train_samples_per_s": round(frames_per_s * TRAIN_B, 1),
+            "sample": f"1/{fraction} of one frame: {sum(nq)} queries (bounces {nq}) + {nt} training samples "
+                      f"+ one Adam step, FP64 with BF16-rounded MLP operands, chunks of {chunk}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the guiding hot path is data-parallel over vertices and "
+              "this build measures one GPU's share (see DESIGN.md for how it shards).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    frame = Frame("bf16")
+    if a.only == "query":
+        (f, xi), (d, p) = frame.q_in[0], frame.q_out[0]
+        for _ in range(a.steps):
+            frame.guide.query(f, xi, dir_out=d, pdf_out=p)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "query", "steps": a.steps}))
+        return
+    if a.only == "records":
+        print(json.dumps({"only": "records", **records_legs(frame, a.steps)}))
+        return
+    if a.only == "train":
+        print(json.dumps({"only": "train", **train_leg(frame, a.steps)}))
+        return
+    ms, wall = time_frames(frame, a.steps, a.warmup, not a.no_graph)
+    nq = sum(BOUNCES)
+    out = {
+        "metric": METRIC,
+        "value": round(nq / (ms * 1e-3), 1),
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "online guiding frame loop: NASG MLP 9->64x4->8*16 (K=16), queries "
+                               "2^20+600000+300000+120000 (fwd+sample+pdf) and one 2^18-sample training "
+                               "step (fwd+bwd+Adam) per frame, HIP graph replay",
+                   "queries_per_frame": nq, "train_samples_per_frame": TRAIN_B,
+                   "hidden": H, "n_hidden": NH, "n_lobes": K, "precision": "bf16"},
+        "train_samples_per_s": round(TRAIN_B / (ms * 1e-3), 1),
+        "frames_per_s": round(1e3 / ms, 2),
+        "wall_s_timed": round(wall, 3),
+    }
+    if a.only != "frame":
+        out["roofline"] = query_roofline(frame)
+        out["records"] = records_legs(frame)
+        out["train_step"] = train_leg(frame)
+    if not a.no_fp32 and a.only != "frame":
+        f32 = Frame("f32")
+        ms32, _ = time_frames(f32, max(5, a.steps // 5), 2, not a.no_graph)
+        out["fp32"] = {"ms_per_step": round(ms32, 4), "value": round(nq / (ms32 * 1e-3), 1),
+                       "train_samples_per_s": round(TRAIN_B / (ms32 * 1e-3), 1),
+                       "speedup_bf16": round(ms32 / ms, 3)}
+        del f32
+    if not a.no_cpu_baseline and a.only != "frame":
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

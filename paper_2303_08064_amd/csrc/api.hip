@@ -1,0 +1,340 @@
+// C ABI of include/nasg.h: host-side validation, workspace carving and
+// kernel launches. No call allocates device memory or synchronises, except
+// nasg_create, which packs the weights and waits for that to finish.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "kernels.hpp"
+#include "nasg.h"
+
+using namespace nasg;
+
+namespace {
+
+thread_local std::string g_err;
+
+nasg_status fail(nasg_status s, const char* fn, const char* what) {
+  g_err = std::string(fn) + ": " + what;
+  return s;
+}
+
+nasg_status hip_fail(const char* fn, hipError_t e) {
+  g_err = std::string(fn) + ": HIP error: " + hipGetErrorString(e);
+  return NASG_E_HIP;
+}
+
+constexpr int kMaxTrainWG = 256;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool compiled(int H, int K, int prec) {
+#define NASG_CASE(h, k, p) if (H == h && K == k && prec == p) return true;
+  NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+  return false;
+}
+
+NetDims dims_of(const nasg_config* c) { return NetDims{c->hidden, c->n_hidden, c->n_lobes}; }
+
+const char* config_error(const nasg_config* c) {
+  if (c == nullptr) return "config is NULL";
+  if (c->n_hidden < 1 || c->n_hidden > 4) return "n_hidden must be in 1..4";
+  if (c->precision != NASG_F32 && c->precision != NASG_BF16) return "precision must be NASG_F32 or NASG_BF16";
+  if (!compiled(c->hidden, c->n_lobes, c->precision))
+    return "unsupported (hidden, n_lobes, precision); compiled: hidden 64 with n_lobes 4, 8, 16";
+  if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
+  if (!(c->lr > 0.0f) || !isfinite(c->lr)) return "lr must be finite and > 0";
+  if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
+    return "beta1 and beta2 must be in [0, 1)";
+  if (!(c->adam_eps > 0.0f) || !isfinite(c->adam_eps)) return "adam_eps must be finite and > 0";
+  if (c->max_batch < 0) return "max_batch must be >= 0";
+  return nullptr;
+}
+
+struct Workspace {
+  size_t partial, loss_partial, norm_partial, step_snapshot, total;
+};
+
+Workspace carve(const nasg_config* c) {
+  const int64_t nw = dims_of(c).num_weights();
+  Workspace w;
+  size_t off = 0;
+  w.partial = off;
+  off = align_up(off + (size_t)kMaxTrainWG * nw * sizeof(float));
+  w.loss_partial = off;
+  off = align_up(off + (size_t)kMaxTrainWG * 2 * sizeof(double));
+  w.norm_partial = off;
+  off = align_up(off + (size_t)reduce_blocks(nw) * sizeof(double));
+  w.step_snapshot = off;
+  off = align_up(off + sizeof(int64_t));
+  w.total = off;
+  return w;
+}
+
+size_t packed_elems(const nasg_config* c) {
+  NetDims d = dims_of(c);
+  return c->precision == NASG_BF16 ? (size_t)Bf16Layout{d}.total_elems() : (size_t)F32Layout{d}.total_elems();
+}
+
+size_t packed_bytes_of(const nasg_config* c) {
+  return packed_elems(c) * (c->precision == NASG_BF16 ? 2 : 4);
+}
+
+// LDS bytes the query kernel copies: the forward part of the packed weights
+size_t query_lds_bytes(const nasg_config* c) {
+  NetDims d = dims_of(c);
+  if (c->precision == NASG_BF16) return (size_t)Bf16Layout{d}.fwd_elems() * 2;
+  return (size_t)F32Layout{d}.total_elems() * 4;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+struct nasg_ctx {
+  nasg_config cfg;
+  nasg_state st;
+  NetDims d;
+  Workspace ws;
+  int num_cus;
+};
+
+extern "C" {
+
+size_t nasg_num_weights(const nasg_config* cfg) {
+  if (cfg == nullptr) return 0;
+  return (size_t)dims_of(cfg).num_weights();
+}
+
+size_t nasg_packed_bytes(const nasg_config* cfg) {
+  if (config_error(cfg) != nullptr) return 0;
+  return packed_bytes_of(cfg);
+}
+
+size_t nasg_workspace_bytes(const nasg_config* cfg) {
+  if (config_error(cfg) != nullptr) return 0;
+  return carve(cfg).total;
+}
+
+const char* nasg_last_error(void) { return g_err.c_str(); }
+
+nasg_status nasg_create(const nasg_config* cfg, const nasg_state* st, nasg_ctx** out) {
+  static const char* fn = "nasg_create";
+  if (out == nullptr) return fail(NASG_E_ARG, fn, "out is NULL");
+  *out = nullptr;
+  if (const char* e = config_error(cfg)) return fail(NASG_E_ARG, fn, e);
+  if (st == nullptr) return fail(NASG_E_ARG, fn, "state is NULL");
+  if (!st->w || !st->grad || !st->adam_m || !st->adam_v || !st->wpack || !st->step || !st->flags || !st->stats ||
+      !st->workspace)
+    return fail(NASG_E_ARG, fn, "a state pointer is NULL");
+  if (!aligned(st->w, 4) || !aligned(st->grad, 4) || !aligned(st->adam_m, 4) || !aligned(st->adam_v, 4) ||
+      !aligned(st->step, 8) || !aligned(st->flags, 4) || !aligned(st->stats, 8))
+    return fail(NASG_E_ALIGN, fn, "state arrays must be naturally aligned");
+  if (!aligned(st->wpack, 16) || !aligned(st->workspace, 16))
+    return fail(NASG_E_ALIGN, fn, "wpack and workspace must be 16-byte aligned");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(fn, e);
+  nasg_ctx* c = new nasg_ctx;
+  c->cfg = *cfg;
+  c->st = *st;
+  c->d = dims_of(cfg);
+  c->ws = carve(cfg);
+  c->num_cus = cus > 0 ? cus : 1;
+  e = launch_pack(st->w, st->wpack, cfg->hidden, cfg->n_hidden, cfg->n_lobes, cfg->precision, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(fn, e);
+  }
+  *out = c;
+  return NASG_OK;
+}
+
+void nasg_destroy(nasg_ctx* ctx) { delete ctx; }
+
+nasg_status nasg_pack(nasg_ctx* ctx, void* stream) {
+  if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_pack", "ctx is NULL");
+  hipError_t e = launch_pack(ctx->st.w, ctx->st.wpack, ctx->d.H, ctx->d.NH, ctx->d.K, ctx->cfg.precision,
+                             (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail("nasg_pack", e);
+}
+
+static nasg_status check_batch(const char* fn, int64_t ld, int64_t B) {
+  if (B < 0) return fail(NASG_E_SHAPE, fn, "B < 0");
+  if (ld < B) return fail(NASG_E_SHAPE, fn, "ld < B");
+  return NASG_OK;
+}
+
+static nasg_status check_ptr(const char* fn, const void* p, const char* name) {
+  if (p == nullptr) return fail(NASG_E_ARG, fn, (std::string(name) + " is NULL").c_str());
+  if (!aligned(p, 4)) return fail(NASG_E_ALIGN, fn, (std::string(name) + " is not 4-byte aligned").c_str());
+  return NASG_OK;
+}
+
+#define NASG_TRY(x)                      \
+  do {                                   \
+    nasg_status s_ = (x);                \
+    if (s_ != NASG_OK) return s_;        \
+  } while (0)
+
+static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, const float* xi, int64_t ld,
+                             int64_t B, float* dir_out, float* pdf_out, float* rec_out, float* raw_out, int mode,
+                             void* stream) {
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  NASG_TRY(check_batch(fn, ld, B));
+  if (B == 0) return NASG_OK;
+  NASG_TRY(check_ptr(fn, feat, "feat"));
+  if (mode == 0) {
+    NASG_TRY(check_ptr(fn, xi, "xi"));
+    NASG_TRY(check_ptr(fn, dir_out, "dir_out"));
+    NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
+    if (rec_out != nullptr && !aligned(rec_out, 4)) return fail(NASG_E_ALIGN, fn, "rec_out is not 4-byte aligned");
+  } else {
+    NASG_TRY(check_ptr(fn, raw_out, "raw_out"));
+  }
+  QueryArgs a;
+  a.wpack = ctx->st.wpack;
+  a.lds_bytes = (int)query_lds_bytes(&ctx->cfg);
+  a.nh = ctx->d.NH;
+  a.eps = ctx->cfg.eps;
+  a.feat = feat;
+  a.xi = xi;
+  a.ld = ld;
+  a.B = B;
+  a.dir_out = dir_out;
+  a.pdf_out = pdf_out;
+  a.rec_out = rec_out;
+  a.raw_out = raw_out;
+  a.num_cus = ctx->num_cus;
+  hipError_t e = launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+nasg_status nasg_forward(nasg_ctx* ctx, const float* feat, int64_t ld, int64_t B, float* raw_out, void* stream) {
+  return run_query(ctx, "nasg_forward", feat, nullptr, ld, B, nullptr, nullptr, nullptr, raw_out, 1, stream);
+}
+
+nasg_status nasg_query(nasg_ctx* ctx, const float* feat, const float* xi, int64_t ld, int64_t B, float* dir_out,
+                       float* pdf_out, float* rec_out, void* stream) {
+  return run_query(ctx, "nasg_query", feat, xi, ld, B, dir_out, pdf_out, rec_out, nullptr, 0, stream);
+}
+
+nasg_status nasg_pdf(nasg_ctx* ctx, const float* rec, const float* dir, int64_t ld, int64_t B, float* pdf_out,
+                     void* stream) {
+  static const char* fn = "nasg_pdf";
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  NASG_TRY(check_batch(fn, ld, B));
+  if (B == 0) return NASG_OK;
+  NASG_TRY(check_ptr(fn, rec, "rec"));
+  NASG_TRY(check_ptr(fn, dir, "dir"));
+  NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
+  RecArgs a{rec, dir, nullptr, ld, B, ctx->cfg.eps, nullptr, pdf_out};
+  hipError_t e = launch_pdf(a, ctx->d.K, (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+nasg_status nasg_sample(nasg_ctx* ctx, const float* rec, const float* xi, int64_t ld, int64_t B, float* dir_out,
+                        float* pdf_out, void* stream) {
+  static const char* fn = "nasg_sample";
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  NASG_TRY(check_batch(fn, ld, B));
+  if (B == 0) return NASG_OK;
+  NASG_TRY(check_ptr(fn, rec, "rec"));
+  NASG_TRY(check_ptr(fn, xi, "xi"));
+  NASG_TRY(check_ptr(fn, dir_out, "dir_out"));
+  NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
+  RecArgs a{rec, nullptr, xi, ld, B, ctx->cfg.eps, dir_out, pdf_out};
+  hipError_t e = launch_sample(a, ctx->d.K, (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
+  const nasg_state& s = ctx->st;
+  unsigned char* ws = static_cast<unsigned char*>(s.workspace);
+  AdamArgs a;
+  a.w = s.w;
+  a.m = s.adam_m;
+  a.v = s.adam_v;
+  a.grad = s.grad;
+  a.wpack = s.wpack;
+  a.step = s.step;
+  a.step_snapshot = reinterpret_cast<const int64_t*>(ws + ctx->ws.step_snapshot);
+  a.flags = s.flags;
+  a.stats = s.stats;
+  a.norm_partial = reinterpret_cast<const double*>(ws + ctx->ws.norm_partial);
+  a.n_norm = reduce_blocks(ctx->d.num_weights());
+  a.n_weights = ctx->d.num_weights();
+  a.H = ctx->d.H;
+  a.NH = ctx->d.NH;
+  a.K = ctx->d.K;
+  a.prec = ctx->cfg.precision;
+  a.lr = ctx->cfg.lr;
+  a.beta1 = ctx->cfg.beta1;
+  a.beta2 = ctx->cfg.beta2;
+  a.adam_eps = ctx->cfg.adam_eps;
+  hipError_t e = launch_adam(a, (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w, int64_t ld,
+                           int64_t B, void* stream) {
+  static const char* fn = "nasg_loss_grad";
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  NASG_TRY(check_batch(fn, ld, B));
+  if (B > ctx->cfg.max_batch) return fail(NASG_E_SHAPE, fn, "B > max_batch");
+  if (B == 0) return fail(NASG_E_SHAPE, fn, "B == 0: the mean loss is undefined");
+  NASG_TRY(check_ptr(fn, feat, "feat"));
+  NASG_TRY(check_ptr(fn, dir, "dir"));
+  NASG_TRY(check_ptr(fn, w, "w"));
+  const nasg_state& s = ctx->st;
+  unsigned char* ws = static_cast<unsigned char*>(s.workspace);
+  const int n_wg = train_workgroups(B, ctx->num_cus);
+  TrainArgs t;
+  t.wpack = s.wpack;
+  t.lds_bytes = (int)packed_bytes_of(&ctx->cfg);
+  t.nh = ctx->d.NH;
+  t.eps = ctx->cfg.eps;
+  t.feat = feat;
+  t.dir = dir;
+  t.w = w;
+  t.ld = ld;
+  t.B = B;
+  t.partial = reinterpret_cast<float*>(ws + ctx->ws.partial);
+  t.loss_partial = reinterpret_cast<double*>(ws + ctx->ws.loss_partial);
+  t.n_weights = ctx->d.num_weights();
+  t.num_cus = ctx->num_cus;
+  hipError_t e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(fn, e);
+  ReduceArgs r;
+  r.partial = t.partial;
+  r.loss_partial = t.loss_partial;
+  r.n_wg = n_wg;
+  r.n_weights = t.n_weights;
+  r.B = B;
+  r.grad = s.grad;
+  r.norm_partial = reinterpret_cast<double*>(ws + ctx->ws.norm_partial);
+  r.stats = s.stats;
+  r.step = s.step;
+  r.step_snapshot = reinterpret_cast<int64_t*>(ws + ctx->ws.step_snapshot);
+  e = launch_reduce(r, reduce_blocks(t.n_weights), (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream) {
+  if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_adam_step", "ctx is NULL");
+  return adam_only(ctx, "nasg_adam_step", stream);
+}
+
+nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w, int64_t ld,
+                            int64_t B, void* stream) {
+  NASG_TRY(nasg_loss_grad(ctx, feat, dir, w, ld, B, stream));
+  return adam_only(ctx, "nasg_train_step", stream);
+}
+
+}  // extern "C"

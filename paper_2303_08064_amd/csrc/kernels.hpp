@@ -1,0 +1,161 @@
+// Kernel argument blocks, shared device helpers and launcher declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+// Network shapes with compiled kernels: (hidden width, lobes, precision).
+#define NASG_FOR_EACH_NET(X) \
+  X(64, 4, 0) X(64, 4, 1) X(64, 8, 0) X(64, 8, 1) X(64, 16, 0) X(64, 16, 1)
+
+namespace nasg {
+
+struct QueryArgs {
+  const void* wpack;
+  int lds_bytes;
+  int nh;
+  float eps;
+  const float* feat;
+  const float* xi;
+  int64_t ld, B;
+  float* dir_out;
+  float* pdf_out;
+  float* rec_out;
+  float* raw_out;
+  int num_cus;
+};
+
+struct RecArgs {
+  const float* rec;
+  const float* dir;   // pdf: directions to evaluate
+  const float* xi;    // sample: uniforms
+  int64_t ld, B;
+  float eps;
+  float* dir_out;
+  float* pdf_out;
+};
+
+struct TrainArgs {
+  const void* wpack;
+  int lds_bytes;
+  int nh;
+  float eps;
+  const float* feat;
+  const float* dir;
+  const float* w;
+  int64_t ld, B;
+  float* partial;        // [n_wg][n_weights] dW partials, canonical layout
+  double* loss_partial;  // [n_wg][2]: sum w*(-log q), sum w
+  int64_t n_weights;
+  int num_cus;
+};
+
+struct ReduceArgs {
+  const float* partial;
+  const double* loss_partial;
+  int n_wg;
+  int64_t n_weights;
+  int64_t B;
+  float* grad;
+  double* norm_partial;  // [n_blocks]
+  double* stats;
+  const int64_t* step;
+  int64_t* step_snapshot;
+};
+
+struct AdamArgs {
+  float* w;
+  float* m;
+  float* v;
+  const float* grad;
+  void* wpack;
+  int64_t* step;
+  const int64_t* step_snapshot;
+  uint32_t* flags;
+  double* stats;
+  const double* norm_partial;
+  int n_norm;
+  int64_t n_weights;
+  int H, NH, K, prec;
+  float lr, beta1, beta2, adam_eps;
+};
+
+// Lobe choice by inverse CDF over k = g*KQ + q (this library's reading: the
+// smallest k with xi_sel * sum(A) < A_0 + ... + A_k; the last lobe with
+// A_k > 0 when rounding leaves none).
+template <int KQ>
+__device__ __forceinline__ int select_lobe(const float (&A)[KQ], float xi, int g, int c) {
+  float cum[KQ];
+  float run = 0.0f;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) { run += A[q]; cum[q] = run; }
+  float t0 = __shfl(run, c), t1 = __shfl(run, c + 16), t2 = __shfl(run, c + 32), t3 = __shfl(run, c + 48);
+  float p01 = t0 + t1, p012 = p01 + t2, total = p012 + t3;
+  float P = g == 0 ? 0.0f : (g == 1 ? t0 : (g == 2 ? p01 : p012));
+  float target = xi * total;
+  int cand = 4 * KQ;
+  int last = -1;
+#pragma unroll
+  for (int q = KQ - 1; q >= 0; --q)
+    if (target < P + cum[q]) cand = g * KQ + q;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+    if (A[q] > 0.0f) last = g * KQ + q;
+  int k = quad_min_i(cand);
+  last = quad_max_i(last);
+  if (k == 4 * KQ) k = last < 0 ? 0 : last;
+  return k;
+}
+
+// The selected lobe's record, from the lane group that owns it.
+template <int KQ>
+__device__ __forceinline__ Lobe broadcast_lobe(const Lobe (&lb)[KQ], int k, int c) {
+  const int gs = k / KQ, qs = k % KQ;
+  Lobe mine = lb[0];
+#pragma unroll
+  for (int q = 1; q < KQ; ++q)
+    if (q == qs) mine = lb[q];
+  const int src = gs * 16 + c;
+  Lobe r;
+  r.zx = __shfl(mine.zx, src);
+  r.zy = __shfl(mine.zy, src);
+  r.zz = __shfl(mine.zz, src);
+  r.xx = __shfl(mine.xx, src);
+  r.xy = __shfl(mine.xy, src);
+  r.xz = __shfl(mine.xz, src);
+  r.lam = __shfl(mine.lam, src);
+  r.a = __shfl(mine.a, src);
+  r.logc = __shfl(mine.logc, src);
+  return r;
+}
+
+// log sum_k exp(ell_k) over the lane's KQ lobes and the vertex's 4 lanes.
+template <int KQ>
+__device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
+  float m = ell[0];
+#pragma unroll
+  for (int q = 1; q < KQ; ++q) m = fmaxf(m, ell[q]);
+  m = quad_max(m);
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) s += fexp(ell[q] - m);
+  s = quad_sum(s);
+  return m == -INFINITY ? -INFINITY : m + flog(s);
+}
+
+hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
+hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
+hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
+hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
+hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
+hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st);
+hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st);
+
+// Query / train kernel grid bounds (workgroups) for a batch of B vertices.
+int train_workgroups(int64_t B, int num_cus);
+int reduce_blocks(int64_t n_weights);
+
+}  // namespace nasg

@@ -1,0 +1,183 @@
+// Wave-level MLP layers on MFMA for one block of 16 vertices.
+//
+// Activations live in the 16x16 accumulator layout: act[mt][i] at lane
+// (g, c) is neuron mt*16 + 4g + i of vertex c. Weights are read from LDS in
+// the layouts of layout.hpp, so each layer's accumulators feed the next layer
+// without any lane exchange (Sec. 4.1: bias-free layers, ReLU between them).
+#pragma once
+
+#include "common.hpp"
+
+namespace nasg {
+
+template <int H, int K, int PREC>
+struct Mlp;
+
+// ---------------------------------------------------------------- BF16 ----
+// 16x16x32 bf16 MFMA with FP32 accumulation; layer 0 uses 16x16x16.
+template <int H, int K>
+struct Mlp<H, K, 1> {
+  static constexpr int MTH = H / 16;     // row tiles of a hidden layer
+  static constexpr int MTO = K / 2;      // row tiles of the output layer (8K/16)
+  static constexpr int KBH = H / 32;     // 32-wide contraction blocks over a hidden layer
+  static constexpr int KBO = K / 4;      // 32-wide contraction blocks over the output (8K/32)
+  typedef bf16x4 Input;
+
+  // features 4g..4g+3 of vertex v: p, omega_o, n, then the constant one, then zeros
+  __device__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+    float f[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = 4 * g + j;
+      float x = 0.0f;
+      if (valid) {
+        if (k < kInFeatures) x = feat[(int64_t)k * ld + v];
+        else if (k == kInFeatures) x = 1.0f;
+      }
+      f[j] = x;
+    }
+    return bf16x4{(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
+  }
+
+  __device__ static bf16x8 operand(const float (&in)[2][4]) {
+    bf16x8 b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = (__bf16)in[j >> 2][j & 3];
+    return b;
+  }
+
+  // h = relu(W_0 x)
+  __device__ static void layer0(const __bf16* lds, Input x, float (&h)[MTH][4], int lane) {
+    const bf16x4* frag = reinterpret_cast<const bf16x4*>(lds);
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt) {
+      f32x4 acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(acc[i], 0.0f);
+    }
+  }
+
+  // out = W in over MT row tiles, W fragments [MT][KBH][64] at `lds`
+  template <int MT>
+  __device__ static void gemm(const __bf16* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+    bf16x8 b[KBH];
+#pragma unroll
+    for (int kb = 0; kb < KBH; ++kb) {
+      float t[2][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { t[0][i] = in[2 * kb][i]; t[1][i] = in[2 * kb + 1][i]; }
+      b[kb] = operand(t);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KBH; ++kb) acc = mfma_bf16_32(frag[(mt * KBH + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[mt][i] = acc[i];
+    }
+  }
+};
+
+// ---------------------------------------------------------------- FP32 ----
+// 16x16x4 f32 MFMA; weights row-major in LDS with an odd pitch.
+template <int H, int K>
+struct Mlp<H, K, 0> {
+  static constexpr int MTH = H / 16;
+  static constexpr int MTO = K / 2;
+  struct Input { float x[3]; };   // features kb*4 + g for kb = 0..2
+
+  __device__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+    Input in;
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb) {
+      int k = kb * 4 + g;
+      float x = 0.0f;
+      if (valid) {
+        if (k < kInFeatures) x = feat[(int64_t)k * ld + v];
+        else if (k == kInFeatures) x = 1.0f;
+      }
+      in.x[kb] = x;
+    }
+    return in;
+  }
+
+  __device__ static void layer0(const float* lds, const Input& x, float (&h)[MTH][4], int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    constexpr int P = kInPadded + 1;
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < 3; ++kb) acc = mfma_f32_4(lds[(mt * 16 + c) * P + kb * 4 + g], x.x[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(acc[i], 0.0f);
+    }
+  }
+
+  // out = W in; W row-major [MT*16][H+1] at `lds`, input neuron of slot (kb, g)
+  // is (kb/4)*16 + 4g + kb%4 = accumulator in[kb/4][kb%4] of this lane
+  template <int MT>
+  __device__ static void gemm(const float* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
+    const int g = lane >> 4, c = lane & 15;
+    constexpr int P = H + 1;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4 acc = zero4();
+      const float* row = lds + (mt * 16 + c) * P + 4 * g;
+#pragma unroll
+      for (int kb = 0; kb < 4 * MTH; ++kb) acc = mfma_f32_4(row[(kb >> 2) * 16 + (kb & 3)], in[kb >> 2][kb & 3], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[mt][i] = acc[i];
+    }
+  }
+};
+
+// Forward through all layers; h[l] keeps hidden activations for the backward.
+template <int H, int K, int PREC, int NHMAX>
+struct Forward {
+  typedef Mlp<H, K, PREC> M;
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
+
+  // offsets (elements) of each layer's forward weights in LDS
+  __device__ static const W* layer_ptr(const W* lds, int l, int nh) {
+    if (PREC == 1) {
+      Bf16Layout Lt{NetDims{H, nh, K}};
+      return lds + Lt.fwd_off(l);
+    } else {
+      F32Layout Lt{NetDims{H, nh, K}};
+      return lds + Lt.off(l);
+    }
+  }
+
+  // h[l] receives hidden layer l's activation for l < nh; `last` the one the
+  // output layer reads (h[nh-1]). Layers past nh are skipped with uniform
+  // branches; no array is indexed by a runtime value.
+  __device__ static void run(const W* lds, int nh, const typename M::Input& x,
+                             float (&h)[NHMAX][M::MTH][4], float (&last)[M::MTH][4],
+                             float (&out)[M::MTO][4], int lane) {
+    M::layer0(layer_ptr(lds, 0, nh), x, h[0], lane);
+#pragma unroll
+    for (int mt = 0; mt < M::MTH; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) last[mt][i] = h[0][mt][i];
+#pragma unroll
+    for (int l = 1; l < NHMAX; ++l) {
+      if (l < nh) {
+        float y[M::MTH][4];
+        M::template gemm<M::MTH>(layer_ptr(lds, l, nh), last, y, lane);
+#pragma unroll
+        for (int mt = 0; mt < M::MTH; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            h[l][mt][i] = fmaxf(y[mt][i], 0.0f);
+            last[mt][i] = h[l][mt][i];
+          }
+      }
+    }
+    M::template gemm<M::MTO>(layer_ptr(lds, nh, nh), last, out, lane);
+  }
+};
+
+}  // namespace nasg

@@ -1,0 +1,276 @@
+// Per-lobe NASG arithmetic in FP32 for gfx950: decode, normaliser, lobe
+// evaluation, direct sampling and the closed-form backward.
+//
+// The formulas are the paper's (eq. NASG and App. A for the lobe, eq. "K for
+// NASG" / App. B for the normaliser, App. C for the sampler, Tab. "decoding"
+// and the Euler frame of Sec. 4.1), rewritten into forms that keep FP32
+// accuracy near the lobe axis:
+//   u = (v.z + 1)/2 = |v + z|^2 / 4,   1 - u = |v - z|^2 / 4,
+//   c^2 = (v.x)^2 / (1 - (v.z)^2) = X^2 / (X^2 + Y^2) with X = v.x, Y = v.y,
+//   log G = 2 lam (u^p - 1) + (p - 1) log u,  p = 1 + eps + a c^2,
+// with log u and u^p - 1 = expm1(p log u) taken through series near u = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nasg {
+
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kLog2Pi = 1.83787706640934548f;   // log(2 pi)
+constexpr float kLogClamp = 15.0f;                // log lambda, log a in [-15, 15]
+
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fsel(bool c, float a, float b) { return c ? a : b; }
+
+// e^x - 1, accurate in relative terms for |x| < 1/4 (Taylor series to x^7,
+// truncation below 2e-9 relative) and through exp elsewhere.
+__device__ __forceinline__ float expm1f_(float x) {
+  float p = fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
+  p = fmaf(x, p, 1.0f / 120.0f);
+  p = fmaf(x, p, 1.0f / 24.0f);
+  p = fmaf(x, p, 1.0f / 6.0f);
+  p = fmaf(x, p, 0.5f);
+  p = fmaf(x, p, 1.0f);
+  p = p * x;
+  float e = fexp(x) - 1.0f;
+  return fsel(fabsf(x) < 0.25f, p, e);
+}
+
+// log(1 + y) for y > -1, accurate in relative terms for |y| < 1/16 (series to
+// y^8, truncation below 2e-10 relative) and through log elsewhere.
+__device__ __forceinline__ float log1pf_(float y) {
+  float p = fmaf(y, -1.0f / 8.0f, 1.0f / 7.0f);
+  p = fmaf(y, p, -1.0f / 6.0f);
+  p = fmaf(y, p, 1.0f / 5.0f);
+  p = fmaf(y, p, -1.0f / 4.0f);
+  p = fmaf(y, p, 1.0f / 3.0f);
+  p = fmaf(y, p, -0.5f);
+  p = fmaf(y, p, 1.0f);
+  p = p * y;
+  float l = flog(1.0f + y);
+  return fsel(fabsf(y) < 0.0625f, p, l);
+}
+
+// tanh(o/2) = 2 sigmoid(o) - 1 (Tab. "decoding") as m/(2 - m) with m = 1 - e^{-|o|},
+// keeping m accurate for small |o|. Returns d; also e = e^{-|o|} and r = 1/(1+e).
+struct Half {
+  float d, e, r;
+};
+__device__ __forceinline__ Half decode_unit(float o) {
+  float ao = fabsf(o);
+  float m = -expm1f_(-ao);
+  float e = 1.0f - m;
+  float r = frcp(2.0f - m);
+  return {copysignf(m * r, o), e, r};
+}
+
+// Decoded lobe: orthonormal frame, sharpness, eccentricity, log normaliser.
+struct Lobe {
+  float zx, zy, zz, xx, xy, xz;
+  float lam, a;
+  float logc;   // log(A_k / K_k), filled once the mixture weights are known
+};
+
+// Euler-angle intermediates kept for the backward pass.
+struct LobeAux {
+  float ct, st, cp, sp, ctau, stau;
+  float h1, h2, h3, h4;     // (1 - d_i^2)/2 = 2 e_i / (1 + e_i)^2 for the sin/cos pairs
+  float inv_np, inv_nt;     // 1/|(d2,d1)|, 1/|(d4,d3)|
+  float loglam, loga;       // clamped raw values
+  bool lam_in, a_in;        // raw values inside the clamp range
+  float logK;
+};
+
+// A (cos, sin) pair divided by its norm; a zero pair becomes (1, 0).
+__device__ __forceinline__ void unit_pair(float c, float s, float& cu, float& su, float& inv) {
+  float n2 = fmaf(c, c, s * s);
+  inv = frsq(n2);
+  bool ok = n2 > 0.0f;
+  cu = fsel(ok, c * inv, 1.0f);
+  su = fsel(ok, s * inv, 0.0f);
+  inv = fsel(ok, inv, 0.0f);
+}
+
+// log K = log(2 pi) + log(1 - e^{-2 lam}) - log lam - (1/2) log((1+eps)(1+eps+a)).
+__device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps) {
+  float one_m = -expm1f_(-2.0f * lam);
+  return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
+}
+
+// Raw outputs o[0..7] of one lobe -> frame, lambda, a, log K (Tab. "decoding",
+// Sec. 4.1 Euler frame). Pair normalisation and the clamp are this library's
+// readings of the paper.
+__device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X) {
+  Half h0 = decode_unit(o[0]);
+  Half h1 = decode_unit(o[1]);
+  Half h2 = decode_unit(o[2]);
+  Half h3 = decode_unit(o[3]);
+  Half h4 = decode_unit(o[4]);
+  X.ct = h0.d;
+  X.st = 2.0f * fsqrt(h0.e) * h0.r;     // sech(o/2) = sqrt(1 - tanh^2)
+  X.h1 = 2.0f * h1.e * h1.r * h1.r;
+  X.h2 = 2.0f * h2.e * h2.r * h2.r;
+  X.h3 = 2.0f * h3.e * h3.r * h3.r;
+  X.h4 = 2.0f * h4.e * h4.r * h4.r;
+  unit_pair(h2.d, h1.d, X.cp, X.sp, X.inv_np);
+  unit_pair(h4.d, h3.d, X.ctau, X.stau, X.inv_nt);
+  L.zx = X.cp * X.st;
+  L.zy = X.sp * X.st;
+  L.zz = X.ct;
+  float ctc = X.ct * X.ctau;
+  L.xx = fmaf(ctc, X.cp, -X.sp * X.stau);
+  L.xy = fmaf(ctc, X.sp, X.cp * X.stau);
+  L.xz = -X.st * X.ctau;
+  X.lam_in = fabsf(o[5]) <= kLogClamp;
+  X.a_in = fabsf(o[6]) <= kLogClamp;
+  X.loglam = fminf(fmaxf(o[5], -kLogClamp), kLogClamp);
+  X.loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
+  L.lam = fexp(X.loglam);
+  L.a = fexp(X.loga);
+  X.logK = log_normaliser(L.lam, X.loglam, L.a, eps);
+  L.logc = 0.0f;
+}
+
+// Lobe value at a unit direction, with what the backward needs.
+struct Eval {
+  float ell;      // log c + log G(v)
+  float L;        // log u
+  float u;        // (v.z + 1)/2
+  float E;        // expm1(p L) = u^p - 1
+  float p, c2;    // exponent and anisotropy weight
+  float X, Y, S;  // v.x, v.y, X^2 + Y^2
+};
+
+__device__ __forceinline__ void cross(float ax, float ay, float az, float bx, float by, float bz,
+                                      float& cx, float& cy, float& cz) {
+  cx = fmaf(ay, bz, -az * by);
+  cy = fmaf(az, bx, -ax * bz);
+  cz = fmaf(ax, by, -ay * bx);
+}
+
+// log G(v) (eq. NASG; App. A with epsilon) for a unit v, plus log c.
+__device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, float vz, float eps) {
+  Eval r;
+  float yx, yy, yz;
+  cross(L.zx, L.zy, L.zz, L.xx, L.xy, L.xz, yx, yy, yz);
+  float dx = vx - L.zx, dy = vy - L.zy, dz = vz - L.zz;
+  float sx = vx + L.zx, sy = vy + L.zy, sz = vz + L.zz;
+  float w = 0.25f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));   // 1 - u
+  float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));   // u
+  // log u: series of log(1 - w) near the axis, else log of the better-conditioned one
+  float lw = log1pf_(-w);
+  float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
+  r.L = fsel(w < 0.0625f, lw, lu);
+  r.u = u;
+  r.X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
+  r.Y = fmaf(vx, yx, fmaf(vy, yy, vz * yz));
+  r.S = fmaf(r.X, r.X, r.Y * r.Y);
+  r.c2 = fsel(r.S > 0.0f, r.X * r.X * frcp(r.S), 0.0f);
+  r.p = 1.0f + eps + L.a * r.c2;
+  r.E = expm1f_(r.p * r.L);
+  float lg = fmaf(2.0f * L.lam, r.E, (r.p - 1.0f) * r.L);
+  // G(-z) = 0: u == 0 only when v = -z exactly
+  r.ell = fsel(u > 0.0f, L.logc + lg, -INFINITY);
+  return r;
+}
+
+// One direction from a single lobe (App. C): (xi0, xi1) -> (s, rho) linearly,
+// xi2 > 1/2 east. Stable form: log s = log(1 + (1 - xi0)(e^{-2 lam} - 1)),
+// (cos theta + 1)/2 = (1 + log s / (2 lam))^{1/p} with p = 1 + eps + a cos^2 phi,
+// and (cos phi, sin phi) proportional to (cos rho, sqrt((1+eps+a)/(1+eps)) sin rho).
+__device__ __forceinline__ void sample_lobe(const Lobe& L, float xi0, float xi1, float xi2,
+                                            float eps, float& vx, float& vy, float& vz) {
+  float t = expm1f_(-2.0f * L.lam);                  // e^{-2 lam} - 1 in (-1, 0)
+  float y0 = (1.0f - xi0) * t;
+  float ls_near = log1pf_(y0);
+  float ls_far = flog(fmaf(1.0f - xi0, fexp(-2.0f * L.lam), xi0));
+  float ls = fsel(y0 > -0.5f, ls_near, ls_far);
+  ls = fmaxf(ls, -2.0f * L.lam);                       // s >= e^{-2 lam}
+  float rr = ls * frcp(2.0f * L.lam);                  // in [-1, 0]
+  rr = fmaxf(rr, -1.0f);
+  // cos(rho) = sin(pi xi1), sin(rho) = -cos(pi xi1); v_sin/v_cos take revolutions
+  float crho = __builtin_amdgcn_sinf(0.5f * xi1);
+  float srho = -__builtin_amdgcn_cosf(0.5f * xi1);
+  float k = fsqrt((1.0f + eps + L.a) * frcp(1.0f + eps));
+  float cphi, sphi, inv;
+  unit_pair(crho, k * srho, cphi, sphi, inv);
+  if (!(xi2 > 0.5f)) { cphi = -cphi; sphi = -sphi; }
+  float p = fmaf(L.a, cphi * cphi, 1.0f + eps);
+  float Lu = log1pf_(rr) * frcp(p);                    // log((cos theta + 1)/2)
+  float u = fexp(Lu);
+  float om = -expm1f_(Lu);                             // 1 - u
+  float ct = 1.0f - 2.0f * om;
+  float st = 2.0f * fsqrt(fmaxf(u * om, 0.0f));
+  float yx, yy, yz;
+  cross(L.zx, L.zy, L.zz, L.xx, L.xy, L.xz, yx, yy, yz);
+  float ax = fmaf(cphi, L.xx, sphi * yx);
+  float ay = fmaf(cphi, L.xy, sphi * yy);
+  float az = fmaf(cphi, L.xz, sphi * yz);
+  vx = fmaf(st, ax, ct * L.zx);
+  vy = fmaf(st, ay, ct * L.zy);
+  vz = fmaf(st, az, ct * L.zz);
+}
+
+// d(loss)/d(raw outputs) of one lobe. gk = dLoss/d ell_k (= g r_k with
+// r_k the lobe's responsibility), galpha = dLoss/d logit_k (= g (r_k - A_k)).
+// Derivation: ell = logA - logK + log G with
+//   d(-logK)/d log lam = 1 - 2 lam / expm1(2 lam),  d(-logK)/d log a = a / (2 (1+eps+a)),
+//   d logG/d log lam = 2 lam E,  d logG/d p = L (2 lam e^{pL} + 1),
+//   d logG/d L = 2 lam p e^{pL} + p - 1,  dL/d(v.z) = 1/(2u),
+//   d c^2/dX = 2 X Y^2 / S^2,  d c^2/dY = -2 Y X^2 / S^2,
+// then through X = v.x, Y = v.y, v.z to the Euler sines/cosines, the pair
+// normalisation and tanh(o/2)' = (1 - d^2)/2.
+__device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, const Eval& e,
+                                              float vx, float vy, float vz, float eps,
+                                              float gk, float galpha, float g[8]) {
+  bool live = e.u > 0.0f && gk != 0.0f;
+  float epl = e.E + 1.0f;
+  float twolam = 2.0f * L.lam;
+  // log lambda
+  float q = twolam * frcp(expm1f_(twolam));     // 2 lam / expm1(2 lam); -> 0 for large lam
+  q = fsel(twolam > 80.0f, 0.0f, q);
+  g[5] = fsel(A.lam_in && live, gk * (twolam * e.E - q + 1.0f), 0.0f);
+  // log a
+  float Dp = e.L * fmaf(twolam, epl, 1.0f);
+  float ga = L.a * fmaf(e.c2, Dp, 0.5f * frcp(1.0f + eps + L.a));
+  g[6] = fsel(A.a_in && live, gk * ga, 0.0f);
+  g[7] = galpha;
+  // direction terms
+  float DL = fmaf(twolam * e.p, epl, e.p - 1.0f);
+  float gZ = fsel(live, gk * DL * frcp(2.0f * e.u), 0.0f);
+  float invS = frcp(e.S);
+  float coef = fsel(live && e.S > 0.0f, gk * L.a * Dp * 2.0f * invS * invS, 0.0f);
+  float gX = coef * e.X * e.Y * e.Y;
+  float gY = -coef * e.Y * e.X * e.X;
+  // X = ctau R + stau Q, Y = -stau R + ctau Q, Zc = st P + ct vz, R = ct P - st vz
+  float P = fmaf(vx, A.cp, vy * A.sp);
+  float Q = fmaf(-vx, A.sp, vy * A.cp);
+  float R = fmaf(A.ct, P, -A.st * vz);
+  float gR = fmaf(A.ctau, gX, -A.stau * gY);
+  float gQ = fmaf(A.stau, gX, A.ctau * gY);
+  float g_ctau = fmaf(R, gX, Q * gY);
+  float g_stau = fmaf(Q, gX, -R * gY);
+  float gP = fmaf(A.st, gZ, A.ct * gR);
+  float g_ct = fmaf(vz, gZ, P * gR);
+  float g_st = fmaf(P, gZ, -vz * gR);
+  float g_cp = fmaf(vx, gP, vy * gQ);
+  float g_sp = fmaf(vy, gP, -vx * gQ);
+  // theta: ct = tanh(o0/2), st = sech(o0/2): dct/do0 = st^2/2, dst/do0 = -st ct/2
+  g[0] = 0.5f * A.st * fmaf(A.st, g_ct, -A.ct * g_st);
+  // (cp, sp) = (d2, d1)/n: d/d d1 = cp t, d/d d2 = -sp t with t = (cp g_sp - sp g_cp)/n
+  float tp = fmaf(A.cp, g_sp, -A.sp * g_cp) * A.inv_np;
+  float tt = fmaf(A.ctau, g_stau, -A.stau * g_ctau) * A.inv_nt;
+  // tanh'(o/2) = (1 - d^2)/2
+  g[1] = A.cp * tp * A.h1;
+  g[2] = -A.sp * tp * A.h2;
+  g[3] = A.ctau * tt * A.h3;
+  g[4] = -A.stau * tt * A.h4;
+}
+
+}  // namespace nasg

@@ -1,0 +1,160 @@
+// Fused guiding query: MLP forward on MFMA (weights LDS-resident), NASG
+// decode, inverse-CDF lobe choice, direct sampling (App. C) and the mixture
+// pdf at the sampled direction (Sec. 3.1), one wave per 16 vertices.
+//
+// Lane (g, c) of a wave owns vertex c of its 16-vertex block and lobes
+// g*K/4 .. g*K/4 + K/4 - 1 of that vertex, so reductions over lobes are a
+// within-lane loop plus two cross-lane steps (xor 16, xor 32).
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "mlp.hpp"
+
+namespace nasg {
+
+template <int H, int K, int PREC, int MODE>   // MODE 0: query, 1: raw forward only
+__global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
+  constexpr int NHMAX = 4;
+  constexpr int KQ = K / 4;
+  typedef Mlp<H, K, PREC> M;
+  typedef Forward<H, K, PREC, NHMAX> F;
+  typedef typename F::W W;
+  extern __shared__ __align__(16) unsigned char smem[];
+  W* lds = reinterpret_cast<W*>(smem);
+  block_copy_to_lds(lds, a.wpack, a.lds_bytes);
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int g = lane >> 4, c = lane & 15;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n_tiles = (a.B + kTileV - 1) / kTileV;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t v = tile * kTileV + c;
+    const bool valid = v < a.B;
+    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    float h[NHMAX][M::MTH][4];
+    float last[M::MTH][4];
+    float out[M::MTO][4];
+    F::run(lds, a.nh, x, h, last, out, lane);
+
+    if (MODE == 1) {
+      // raw outputs in canonical row order: accumulator t of lane group g is
+      // parameter t / KQ of lobe g*KQ + t % KQ
+      if (valid) {
+#pragma unroll
+        for (int t = 0; t < 2 * K; ++t) {
+          int p = t / KQ, k = g * KQ + t % KQ;
+          a.raw_out[(int64_t)(p * K + k) * a.ld + v] = out[t >> 2][t & 3];
+        }
+      }
+      continue;
+    }
+
+    // ---- decode (Tab. "decoding", Euler frame of Sec. 4.1) ----
+    Lobe lb[KQ];
+    float logK[KQ], alpha[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      float o[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        int t = p * KQ + q;
+        o[p] = out[t >> 2][t & 3];
+      }
+      LobeAux aux;
+      decode_lobe(o, a.eps, lb[q], aux);
+      logK[q] = aux.logK;
+      alpha[q] = o[7];
+    }
+    // mixture weights: softmax over the K logits
+    float mx = alpha[0];
+#pragma unroll
+    for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
+    mx = quad_max(mx);
+    float se = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
+    se = quad_sum(se);
+    const float lse = mx + flog(se);
+    float A[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      float logA = alpha[q] - lse;
+      lb[q].logc = logA - logK[q];
+      A[q] = fexp(logA);
+    }
+
+    // ---- inverse-CDF lobe choice over k = g*KQ + q ----
+    float xi_sel = 0.0f, xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
+    if (valid) {
+      xi_sel = a.xi[v];
+      xi0 = a.xi[a.ld + v];
+      xi1 = a.xi[2 * a.ld + v];
+      xi2 = a.xi[3 * a.ld + v];
+    }
+    int ksel = select_lobe<KQ>(A, xi_sel, g, c);
+    Lobe s = broadcast_lobe<KQ>(lb, ksel, c);
+
+    // ---- sample (App. C) and evaluate the mixture there ----
+    float vx, vy, vz;
+    sample_lobe(s, xi0, xi1, xi2, a.eps, vx, vy, vz);
+    float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    vx *= inv; vy *= inv; vz *= inv;
+    float ell[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe(lb[q], vx, vy, vz, a.eps).ell;
+    float logq = mixture_lse<KQ>(ell);
+
+    if (valid && g == 0) {
+      a.dir_out[v] = vx;
+      a.dir_out[a.ld + v] = vy;
+      a.dir_out[2 * a.ld + v] = vz;
+      a.pdf_out[v] = fexp(logq);
+    }
+    if (a.rec_out != nullptr && valid) {
+      float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const int k = g * KQ + q;
+        const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz,
+                               lb[q].lam, lb[q].a, lb[q].logc};
+#pragma unroll
+        for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
+      }
+    }
+  }
+}
+
+template <int H, int K, int PREC>
+static hipError_t launch_query_t(const QueryArgs& a, int mode, hipStream_t st) {
+  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0> : query_kernel<H, K, PREC, 1>;
+  // occupancy depends on the LDS footprint; cache it per (mode, footprint)
+  static int cached_bytes[2] = {-1, -1};
+  static int cached_per_cu[2] = {1, 1};
+  if (cached_bytes[mode] != a.lds_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, a.lds_bytes);
+    if (e != hipSuccess) return e;
+    cached_per_cu[mode] = per_cu < 1 ? 1 : per_cu;
+    cached_bytes[mode] = a.lds_bytes;
+  }
+  const int64_t n_tiles = (a.B + kTileV - 1) / kTileV;
+  const int64_t want = (n_tiles + 3) / 4;
+  const int64_t cap = (int64_t)cached_per_cu[mode] * a.num_cus;
+  int grid = (int)(want < cap ? want : cap);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), a.lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st) {
+#define NASG_CASE(h, k, p) \
+  if (H == h && K == k && prec == p) return launch_query_t<h, k, p>(a, mode, st);
+  NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nasg

@@ -1,0 +1,534 @@
+// Online training step (Sec. 4.2, Sec. 5): fused forward recompute, weighted
+// NLL, closed-form NASG backward, MLP backward on MFMA; then a fixed-order
+// reduction of per-workgroup weight gradients and a fused Adam update.
+//
+// Work split of the fused kernel (one persistent workgroup of 4 waves per CU):
+// each wave runs forward, NASG backward and dgrad for its own 16 vertices with
+// activations in registers (nothing is written to HBM); for the weight
+// gradient dW_l = sum_v delta_l(v) h_{l-1}(v)^T the four waves stage delta_l
+// and h_{l-1} of the workgroup's 64 vertices in LDS and each wave accumulates
+// its own rows of dW_l in registers across every tile the workgroup visits.
+// Every sum has a fixed order, so results are bitwise reproducible.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "mlp.hpp"
+
+namespace nasg {
+
+constexpr int kMaxTrainWG = 256;
+constexpr int kWGV = 64;   // vertices per workgroup tile
+
+template <int H, int K, int PREC>
+struct TrainCfg {
+  typedef Mlp<H, K, PREC> M;
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type S;   // staging type
+  static constexpr int NHMAX = 4;
+  static constexpr int KQ = K / 4;
+  static constexpr int MTH = H / 16, MTO = K / 2;
+  static constexpr int RMAX = (8 * K > H) ? 8 * K : H;   // rows of the largest delta
+  static constexpr int SP = PREC == 1 ? kWGV + 8 : kWGV + 4;   // staging pitch (elements)
+  static constexpr int RTW_H = (MTH + 3) / 4;   // row tiles of dW per wave, hidden layers
+  static constexpr int RTW_O = (MTO + 3) / 4;   // row tiles of dW per wave, output layer
+  static constexpr int CTH = H / 16;            // column tiles of dW (hidden input)
+  static constexpr int stage_elems() { return (RMAX + H) * SP; }
+};
+
+// weights of layer l in LDS (forward and, for l >= 1, backward)
+template <int H, int K, int PREC>
+struct TrainLds {
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
+  __device__ static const W* fwd(const W* lds, int l, int nh) {
+    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K}}.fwd_off(l);
+    return lds + F32Layout{NetDims{H, nh, K}}.off(l);
+  }
+  __device__ static const W* bwd(const W* lds, int l, int nh) {
+    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K}}.bwd_off(l);
+    return lds + F32Layout{NetDims{H, nh, K}}.off(l);
+  }
+};
+
+// delta_prev = W_l^T delta (contraction over the RT*16 rows of layer l),
+// rows of the result are the previous layer's neurons in accumulator layout.
+template <int H, int K, int PREC, int RT>
+__device__ __forceinline__ void dgrad(const void* wl, int rows_pitch_unused, const float (&dl)[RT][4],
+                                      float (&dp)[H / 16][4], int lane) {
+  constexpr int MTP = H / 16;
+  if constexpr (PREC == 1) {
+    constexpr int KB = RT / 2;   // 32-wide blocks over the rows of layer l
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(wl);
+    bf16x8 b[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
+    }
+  } else {
+    const float* W = reinterpret_cast<const float*>(wl);
+    constexpr int P = H + 1;
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < 4 * RT; ++kb) {
+        // row R of layer l fed by slot (kb, g): accumulator dl[kb/4][kb%4]
+        const int R = (kb >> 2) * 16 + 4 * g + (kb & 3);
+        acc = mfma_f32_4(W[R * P + mt * 16 + c], dl[kb >> 2][kb & 3], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
+    }
+  }
+}
+
+// Write a wave's accumulator-layout block [RT*16 rows][16 vertices] into the
+// staging buffer at vertex column wave*16.
+template <typename S, int RT, int SP>
+__device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int wave, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) buf[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (S)x[mt][i];
+}
+
+// acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the 64 staged vertices
+template <int PREC, typename S, int SP, int NR, int NC>
+__device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const int (&rt)[NR], int nrt,
+                                            f32x4 (&acc)[NR][NC], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  if constexpr (PREC == 1) {
+#pragma unroll
+    for (int vb = 0; vb < kWGV / 32; ++vb) {
+      bf16x8 hb[NC];
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct)
+        hb[ct] = *reinterpret_cast<const bf16x8*>(hst + (ct * 16 + c) * SP + vb * 32 + 8 * g);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nrt) {
+          bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + (rt[r] * 16 + c) * SP + vb * 32 + 8 * g);
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_bf16_32(da, hb[ct], acc[r][ct]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int vb = 0; vb < kWGV / 4; ++vb) {
+      float hb[NC];
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct) hb[ct] = hst[(ct * 16 + c) * SP + vb * 4 + g];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nrt) {
+          float da = dst[(rt[r] * 16 + c) * SP + vb * 4 + g];
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_f32_4(da, hb[ct], acc[r][ct]);
+        }
+      }
+    }
+  }
+}
+
+// Flush a wave's dW tiles of layer l to the workgroup's canonical partial.
+template <int NR, int NC>
+__device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,
+                                            const f32x4 (&acc)[NR][NC], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  const int cols = d.cols(l);
+  const int64_t off = d.canon_off(l);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nrt) continue;
+#pragma unroll
+    for (int ct = 0; ct < NC; ++ct) {
+      const int k = ct * 16 + c;
+      if (k >= cols) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int R = rt[r] * 16 + 4 * g + i;
+        const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
+        part[off + (int64_t)n * cols + k] = acc[r][ct][i];
+      }
+    }
+  }
+}
+
+template <int H, int K, int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void train_kernel(TrainArgs a) {
+  typedef TrainCfg<H, K, PREC> C;
+  typedef typename C::M M;
+  typedef typename C::S S;
+  typedef TrainLds<H, K, PREC> TL;
+  typedef typename TL::W W;
+  constexpr int NHMAX = C::NHMAX, KQ = C::KQ, MTH = C::MTH, MTO = C::MTO, SP = C::SP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  W* lds = reinterpret_cast<W*>(smem);
+  S* dst = reinterpret_cast<S*>(smem + a.lds_bytes);     // delta staging [RMAX][SP]
+  S* hst = dst + C::RMAX * SP;                            // input staging [H][SP]
+  block_copy_to_lds(lds, a.wpack, a.lds_bytes);
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int g = lane >> 4, c = lane & 15;
+  const int wave = threadIdx.x >> 6;
+  const int nh = a.nh;
+  const NetDims dims{H, nh, K};
+  const float inv_b = 1.0f / (float)a.B;
+
+  // this wave's dW row tiles per layer: rt = wave, wave + 4, ...
+  int rt_h[C::RTW_H], rt_o[C::RTW_O];
+  int nrt_h = 0, nrt_o = 0;
+#pragma unroll
+  for (int r = 0; r < C::RTW_H; ++r) { rt_h[r] = wave + 4 * r; if (rt_h[r] < MTH) nrt_h = r + 1; }
+#pragma unroll
+  for (int r = 0; r < C::RTW_O; ++r) { rt_o[r] = wave + 4 * r; if (rt_o[r] < MTO) nrt_o = r + 1; }
+
+  f32x4 acc0[C::RTW_H][1];
+  f32x4 acch[NHMAX - 1][C::RTW_H][C::CTH];
+  f32x4 acco[C::RTW_O][C::CTH];
+#pragma unroll
+  for (int r = 0; r < C::RTW_H; ++r) {
+    acc0[r][0] = zero4();
+#pragma unroll
+    for (int l = 0; l < NHMAX - 1; ++l)
+#pragma unroll
+      for (int ct = 0; ct < C::CTH; ++ct) acch[l][r][ct] = zero4();
+  }
+#pragma unroll
+  for (int r = 0; r < C::RTW_O; ++r)
+#pragma unroll
+    for (int ct = 0; ct < C::CTH; ++ct) acco[r][ct] = zero4();
+  double loss_sum = 0.0, w_sum = 0.0;
+
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t v = tile * kWGV + wave * 16 + c;
+    const bool valid = v < a.B;
+    // ---- forward (recomputed) ----
+    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    float h[NHMAX][MTH][4];
+    float last[MTH][4];
+    float out[MTO][4];
+    Forward<H, K, PREC, NHMAX>::run(lds, nh, x, h, last, out, lane);
+
+    // ---- weighted NLL and its gradient w.r.t. the raw outputs ----
+    float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f;
+    if (valid) {
+      vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
+      wj = a.w[v];
+      float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+      vx *= inv; vy *= inv; vz *= inv;
+    }
+    Lobe lb[KQ];
+    LobeAux ax[KQ];
+    float alpha[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      float o[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) { const int t = p * KQ + q; o[p] = out[t >> 2][t & 3]; }
+      decode_lobe(o, a.eps, lb[q], ax[q]);
+      alpha[q] = o[7];
+    }
+    float mx = alpha[0];
+#pragma unroll
+    for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
+    mx = quad_max(mx);
+    float se = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
+    se = quad_sum(se);
+    const float lse = mx + flog(se);
+    float logA[KQ];
+    Eval ev[KQ];
+    float ell[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      logA[q] = alpha[q] - lse;
+      lb[q].logc = logA[q] - ax[q].logK;
+      ev[q] = eval_lobe(lb[q], vx, vy, vz, a.eps);
+      ell[q] = ev[q].ell;
+    }
+    const float logq = mixture_lse<KQ>(ell);
+    const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q
+    if (valid && g == 0) {
+      loss_sum += (double)wj * (double)(-logq);
+      w_sum += (double)wj;
+    }
+    float dl[MTO][4];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const float r = valid ? fexp(ell[q] - logq) : 0.0f;
+      const float Aq = fexp(logA[q]);
+      float gq[8];
+      backward_lobe(lb[q], ax[q], ev[q], vx, vy, vz, a.eps, gs * r, gs * (r - Aq), gq);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) { const int t = p * KQ + q; dl[t >> 2][t & 3] = gq[p]; }
+    }
+
+    // ---- MLP backward: output layer ----
+    float dh[MTH][4];
+    {
+      stage_rows<S, MTO, SP>(dst, dl, wave, lane);
+      stage_rows<S, MTH, SP>(hst, last, wave, lane);
+      dgrad<H, K, PREC, MTO>(TL::bwd(lds, nh, nh), 0, dl, dh, lane);
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
+      __syncthreads();
+      wgrad_tiles<PREC, S, SP, C::RTW_O, C::CTH>(dst, hst, rt_o, nrt_o, acco, lane);
+      __syncthreads();
+    }
+    // ---- hidden layers l = nh-1 .. 1 ----
+#pragma unroll
+    for (int l = NHMAX - 1; l >= 1; --l) {
+      if (l >= nh) continue;
+      float prev[MTH][4];
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) prev[mt][i] = h[l - 1][mt][i];
+      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
+      stage_rows<S, MTH, SP>(hst, prev, wave, lane);
+      float dn[MTH][4];
+      dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), 0, dh, dn, lane);
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dn[mt][i] = prev[mt][i] > 0.0f ? dn[mt][i] : 0.0f;
+      __syncthreads();
+      wgrad_tiles<PREC, S, SP, C::RTW_H, C::CTH>(dst, hst, rt_h, nrt_h, acch[l - 1], lane);
+      __syncthreads();
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dh[mt][i] = dn[mt][i];
+    }
+    // ---- layer 0: input = features, constant one, zero padding ----
+    {
+      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
+      // input rows 0..15 for this wave's 16 vertices: lane (g, c) writes rows 4g..4g+3
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * g + j;
+        float xv = 0.0f;
+        if (valid) {
+          if (k < kInFeatures) xv = a.feat[(int64_t)k * a.ld + v];
+          else if (k == kInFeatures) xv = 1.0f;
+        }
+        hst[k * SP + wave * 16 + c] = (S)xv;
+      }
+      __syncthreads();
+      wgrad_tiles<PREC, S, SP, C::RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      __syncthreads();
+    }
+  }
+
+  // ---- flush this workgroup's partial sums ----
+  float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
+  flush_tiles<C::RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
+#pragma unroll
+  for (int l = 1; l < NHMAX; ++l)
+    if (l < nh) flush_tiles<C::RTW_H, C::CTH>(part, dims, l, rt_h, nrt_h, acch[l - 1], lane);
+  flush_tiles<C::RTW_O, C::CTH>(part, dims, nh, rt_o, nrt_o, acco, lane);
+
+  // loss partials: wave reduction, then the four waves in order
+  __shared__ double red[4][2];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    loss_sum += __shfl_xor(loss_sum, s);
+    w_sum += __shfl_xor(w_sum, s);
+  }
+  if (lane == 0) { red[wave][0] = loss_sum; red[wave][1] = w_sum; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.loss_partial[2 * blockIdx.x] = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+    a.loss_partial[2 * blockIdx.x + 1] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+  }
+}
+
+int train_workgroups(int64_t B, int num_cus) {
+  int64_t t = (B + kWGV - 1) / kWGV;
+  int cap = num_cus < kMaxTrainWG ? num_cus : kMaxTrainWG;
+  return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
+}
+
+template <int H, int K, int PREC>
+static hipError_t launch_train_t(const TrainArgs& a, int n_wg, hipStream_t st) {
+  typedef TrainCfg<H, K, PREC> C;
+  size_t shmem = (size_t)a.lds_bytes + sizeof(typename C::S) * C::stage_elems();
+  auto kern = train_kernel<H, K, PREC>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(n_wg), dim3(256), shmem, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st) {
+#define NASG_CASE(h, k, p) \
+  if (H == h && K == k && prec == p) return launch_train_t<h, k, p>(a, n_wg, st);
+  NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- reduce ----
+// grad[i] = sum over workgroups (fixed order, FP64) of partial[wg][i];
+// per-block FP64 sums of grad^2; block 0 also totals the loss.
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (i < a.n_weights) {
+    for (int wg = 0; wg < a.n_wg; ++wg) s += (double)a.partial[(int64_t)wg * a.n_weights + i];
+    a.grad[i] = (float)s;
+  }
+  double gsq = i < a.n_weights ? (double)(float)s * (double)(float)s : 0.0;
+  __shared__ double red[256];
+  red[threadIdx.x] = gsq;
+  __syncthreads();
+  for (int k = 128; k >= 1; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.norm_partial[blockIdx.x] = red[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double ls = 0.0, ws = 0.0;
+    for (int wg = 0; wg < a.n_wg; ++wg) { ls += a.loss_partial[2 * wg]; ws += a.loss_partial[2 * wg + 1]; }
+    a.stats[0] = ls / (double)a.B;
+    a.stats[1] = ws;
+    a.stats[3] = ls;
+    *a.step_snapshot = *a.step;
+  }
+}
+
+int reduce_blocks(int64_t n_weights) { return (int)((n_weights + 255) / 256); }
+
+hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(n_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ adam ----
+__device__ __forceinline__ void locate(const NetDims& d, int64_t i, int& l, int& n, int& k) {
+  l = 0;
+  for (int t = 1; t <= d.NH; ++t)
+    if (i >= d.canon_off(t)) l = t;
+  const int64_t r = i - d.canon_off(l);
+  n = (int)(r / d.cols(l));
+  k = (int)(r % d.cols(l));
+}
+
+__device__ __forceinline__ void write_packed(const AdamArgs& a, const NetDims& d, int64_t i, float w) {
+  int l, n, k;
+  locate(d, i, l, n, k);
+  if (a.prec == 1) {
+    Bf16Layout Lt{d};
+    __bf16* p = reinterpret_cast<__bf16*>(a.wpack);
+    const __bf16 b = (__bf16)w;
+    p[bf16_fwd_pos(Lt, l, n, k)] = b;
+    if (l >= 1) p[bf16_bwd_pos(Lt, l, n, k)] = b;
+  } else {
+    F32Layout Lt{d};
+    reinterpret_cast<float*>(a.wpack)[f32_pos(Lt, l, n, k)] = w;
+  }
+}
+
+// Kingma and Ba's Adam, bias-corrected, no weight decay; skipped (weights,
+// moments and step unchanged, flag bit 0 set) if the loss or the gradient norm
+// is not finite.
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < a.n_norm; j += 256) s += a.norm_partial[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k >= 1; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double nsq = red[0];
+  const double loss = a.stats[0];
+  const bool skip = !isfinite(loss) || !isfinite(nsq);
+  const int64_t t0 = *a.step_snapshot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.stats[2] = sqrt(nsq);
+    *a.flags = skip ? 1u : 0u;
+    *a.step = skip ? t0 : t0 + 1;
+  }
+  if (skip) return;
+  const double t = (double)(t0 + 1);
+  const float bc1 = (float)(1.0 - pow((double)a.beta1, t));
+  const float bc2_sqrt = (float)sqrt(1.0 - pow((double)a.beta2, t));
+  const float step_size = a.lr / bc1;
+  const NetDims d{a.H, a.NH, a.K};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n_weights; i += (int64_t)gridDim.x * 256) {
+    const float gi = a.grad[i];
+    const float m = fmaf(a.beta1, a.m[i], (1.0f - a.beta1) * gi);
+    const float v = fmaf(a.beta2, a.v[i], (1.0f - a.beta2) * gi * gi);
+    const float denom = sqrtf(v) / bc2_sqrt + a.adam_eps;
+    const float w = a.w[i] - step_size * (m / denom);
+    a.m[i] = m;
+    a.v[i] = v;
+    a.w[i] = w;
+    write_packed(a, d, i, w);
+  }
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t st) {
+  int grid = (int)((a.n_weights + 255) / 256);
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(adam_kernel, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pack ----
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ w, void* wpack, NetDims d, int prec,
+                                                   int64_t n_elems) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_elems; e += (int64_t)gridDim.x * 256) {
+    int l, n, k;
+    if (prec == 1) bf16_source(Bf16Layout{d}, e, l, n, k);
+    else f32_source(F32Layout{d}, e, l, n, k);
+    float x = k < 0 ? 0.0f : w[d.canon_off(l) + (int64_t)n * d.cols(l) + k];
+    if (prec == 1) reinterpret_cast<__bf16*>(wpack)[e] = (__bf16)x;
+    else reinterpret_cast<float*>(wpack)[e] = x;
+  }
+}
+
+hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st) {
+  NetDims d{H, NH, K};
+  int64_t n = prec == 1 ? Bf16Layout{d}.total_elems() : F32Layout{d}.total_elems();
+  int grid = (int)((n + 255) / 256);
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, st, w, wpack, d, prec, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(uint32_t* p, int64_t n, uint32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = value;
+}
+
+hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st) {
+  if (n_words <= 0) return hipSuccess;
+  int grid = (int)((n_words + 255) / 256);
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(p), n_words, value);
+  return hipGetLastError();
+}
+
+}  // namespace nasg

@@ -1,0 +1,78 @@
+"""Host-side checks: kernel weight layouts and the C ABI's exports (no GPU)."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nasg.h")
+CSRC = os.path.join(ROOT, "paper_2303_08064_amd", "csrc")
+
+
+def test_weight_layouts_are_bijections(tmp_path):
+    exe = tmp_path / "layout_check"
+    src = os.path.join(ROOT, "tests", "layout_check.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, src, "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(nasg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list():
+    from paper_2303_08064_amd import _lib
+    assert header_functions() == sorted(_lib.EXPORTED)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2303_08064_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libnasg.so is not built; run `python -m paper_2303_08064_amd.build`")
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def _cfg(**kw):
+    from paper_2303_08064_amd._lib import Config
+    base = dict(hidden=64, n_hidden=4, n_lobes=16, precision=1, eps=0.0, lr=1e-3, beta1=0.9,
+                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18)
+    base.update(kw)
+    return Config(**base)
+
+
+def test_size_queries(lib):
+    c = _cfg()
+    assert lib.nasg_num_weights(ctypes.byref(c)) == 21120
+    # bf16 fragments: forward 16H + 3H^2 + 8KH, backward 3H^2 + 8KH, 2 bytes each
+    assert lib.nasg_packed_bytes(ctypes.byref(c)) == 2 * (1024 + 3 * 4096 + 8192 + 3 * 4096 + 8192)
+    c32 = _cfg(precision=0, n_lobes=8)
+    assert lib.nasg_num_weights(ctypes.byref(c32)) == 17024
+    assert lib.nasg_packed_bytes(ctypes.byref(c32)) == 4 * (64 * 17 + 3 * 64 * 65 + 64 * 65)
+    ws = lib.nasg_workspace_bytes(ctypes.byref(c))
+    assert ws >= 256 * 21120 * 4
+    # unsupported configurations report zero sizes
+    assert lib.nasg_packed_bytes(ctypes.byref(_cfg(hidden=48))) == 0
+    assert lib.nasg_workspace_bytes(ctypes.byref(_cfg(n_lobes=5))) == 0
+
+
+def test_create_validates_on_host(lib):
+    from paper_2303_08064_amd._lib import State, NASG_E_ARG
+    ctx = ctypes.c_void_p()
+    st = State()
+    assert lib.nasg_create(ctypes.byref(_cfg()), ctypes.byref(st), ctypes.byref(ctx)) == NASG_E_ARG
+    assert b"NULL" in lib.nasg_last_error()
+    assert lib.nasg_create(ctypes.byref(_cfg(n_hidden=9)), ctypes.byref(st), ctypes.byref(ctx)) == NASG_E_ARG
+    assert b"n_hidden" in lib.nasg_last_error()
+    assert lib.nasg_create(ctypes.byref(_cfg(lr=-1.0)), ctypes.byref(st), ctypes.byref(ctx)) == NASG_E_ARG
+    assert lib.nasg_query(None, None, None, 0, 0, None, None, None, None) == NASG_E_ARG
