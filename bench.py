@@ -63,7 +63,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-graph", action="store_true")
-    p.add_argument("--only", choices=["frame", "query", "records", "train"], default=None,
+    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy"], default=None,
                    help="run one leg only (for profilers)")
     return p.parse_args()
 
@@ -222,43 +222,55 @@ def train_leg(frame, reps=10):
     return {"avg_ms": round(ms, 4), "samples_per_s": round(TRAIN_B / (ms * 1e-3), 1)}
 
 
-def cpu_baseline(fraction=4):
-    """The FP64 oracle on the host: 1/fraction of a frame's queries (each bounce
-    scaled) and training samples, timed; reported in queries/s of frames."""
+def cpu_baseline(min_seconds=10.0, max_pieces=64, fraction=8):
+    """The FP64 oracle on the host for a bounded sample of the frame: pieces
+    of 1/fraction of a frame (every bounce's queries and the training samples
+    scaled by 1/fraction, plus one Adam step each) until min_seconds have
+    passed; reported in queries/s of whole frames."""
     import torch
     from oracle import mlp as omlp, nasg as onasg, train as otrain
     from paper_2303_08064_amd import synth
     mats = synth.init_weights(synth.layer_shapes(H, NH, K), synth.rng_for(42))
     W = [torch.tensor(m, dtype=torch.float64) for m in mats]
+    flatW = torch.cat([x.reshape(-1) for x in W])
     rng = synth.rng_for(2000)
+    tgt = synth.VmfTarget(4, seed=1001)
     nq = [n // fraction for n in BOUNCES]
     nt = TRAIN_B // fraction
     chunk = 65536
-    t0 = time.perf_counter()
-    for n in nq:
-        for s in range(0, n, chunk):
-            m = min(chunk, n - s)
-            f, xi = synth.features(m, rng), synth.uniforms(m, rng)
-            lob = onasg.decode(omlp.forward(W, f.T, bf16=True), K)
-            v, _ = onasg.sample(lob, xi.T.astype(np.float64))
-            onasg.mixture_log_pdf(v, lob)
-    tgt = synth.VmfTarget(4, seed=1001)
-    grads = None
-    for s in range(0, nt, chunk):
-        m = min(chunk, nt - s)
-        f, d, w = synth.training_batch(m, rng, tgt)
-        _, gl = otrain.loss_and_grad(W, f.T, d.T, w.astype(np.float64), K, bf16=True)
-        grads = gl if grads is None else [a + b for a, b in zip(grads, gl)]
-    flat = torch.cat([x.reshape(-1) for x in grads])
-    z = torch.zeros_like(flat)
-    otrain.adam_step(torch.cat([x.reshape(-1) for x in W]), flat, z, z.clone(), 0, 1e-3)
-    dt = time.perf_counter() - t0
-    frames_per_s = (1.0 / fraction) / dt
+    pieces = 0
+    dt = 0.0   # oracle compute time only; host generation of inputs is not timed
+    while pieces < max_pieces and (pieces == 0 or dt < min_seconds):
+        for n in nq:
+            for s in range(0, n, chunk):
+                m = min(chunk, n - s)
+                f, xi = synth.features(m, rng), synth.uniforms(m, rng)
+                t0 = time.perf_counter()
+                lob = onasg.decode(omlp.forward(W, f.T, bf16=True), K)
+                v, _ = onasg.sample(lob, xi.T.astype(np.float64))
+                onasg.mixture_log_pdf(v, lob)
+                dt += time.perf_counter() - t0
+        grads = None
+        for s in range(0, nt, chunk):
+            m = min(chunk, nt - s)
+            f, d, w = synth.training_batch(m, rng, tgt)
+            t0 = time.perf_counter()
+            _, gl = otrain.loss_and_grad(W, f.T, d.T, w.astype(np.float64), K, bf16=True)
+            grads = gl if grads is None else [a + b for a, b in zip(grads, gl)]
+            dt += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        flat = torch.cat([x.reshape(-1) for x in grads])
+        z = torch.zeros_like(flat)
+        otrain.adam_step(flatW, flat, z, z.clone(), 0, 1e-3)
+        dt += time.perf_counter() - t0
+        pieces += 1
+    frames_per_s = (pieces / fraction) / dt
     return {"value": round(frames_per_s * sum(BOUNCES), 1), "unit": "queries/s", "cores": torch.get_num_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
             "train_samples_per_s": round(frames_per_s * TRAIN_B, 1),
-            "sample": f"1/{fraction} of one frame: {sum(nq)} queries (bounces {nq}) + {nt} training samples "
-                      f"+ one Adam step, FP64 with BF16-rounded MLP operands, chunks of {chunk}"}
+            "sample": f"{pieces} x 1/{fraction} of a frame (each: {sum(nq)} queries, bounces {nq}, "
+                      f"{nt} training samples, one Adam step); FP64 with BF16-rounded MLP operands; "
+                      f"only the oracle's compute is timed"}
 
 
 def main():
@@ -276,6 +288,16 @@ def main():
             frame.guide.query(f, xi, dir_out=d, pdf_out=p)
         torch.cuda.synchronize()
         print(json.dumps({"only": "query", "steps": a.steps}))
+        return
+    if a.only == "copy":
+        # a plain device copy of known size, to scale the HBM byte counters
+        n = 64 << 20
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(a.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "steps": a.steps}))
         return
     if a.only == "records":
         print(json.dumps({"only": "records", **records_legs(frame, a.steps)}))
