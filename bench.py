@@ -63,7 +63,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-graph", action="store_true")
-    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy"], default=None,
+    p.add_argument("--no-configs", action="store_true")
+    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy", "c5"], default=None,
                    help="run one leg only (for profilers)")
     return p.parse_args()
 
@@ -222,6 +223,78 @@ def train_leg(frame, reps=10):
     return {"avg_ms": round(ms, 4), "samples_per_s": round(TRAIN_B / (ms * 1e-3), 1)}
 
 
+PEAK_F32_MFMA_TFLOPS = 157.3
+
+
+def train_flops(hidden, n_hidden, k):
+    """Algorithmic MFMA FLOPs of one training sample: forward, dgrad through
+    layers L..1 (none into the input) and the weight gradient of every layer."""
+    fwd = mlp_flops(hidden, n_hidden, k)
+    dgrad = 2 * ((n_hidden - 1) * hidden * hidden + 8 * k * hidden)
+    return fwd + dgrad + fwd
+
+
+def config_legs():
+    """The other workload configurations, each timed briefly on its own:
+    C1 one small FP32 step (latency), C2 FP32 training on 2^18 samples, C3
+    BF16 and FP32 inference on 2^20 queries, C5 BF16 training of the large
+    network on 2^22 samples."""
+    import torch
+    from paper_2303_08064_amd import synth
+    from paper_2303_08064_amd.nasg import NasgGuide
+    out = {}
+
+    def guide(hidden, n_hidden, k, prec, max_batch):
+        mats = synth.init_weights(synth.layer_shapes(hidden, n_hidden, k), synth.rng_for(42))
+        return NasgGuide(synth.flat_weights(mats), hidden=hidden, n_hidden=n_hidden, n_lobes=k,
+                         precision=prec, max_batch=max_batch)
+
+    def batch(n, seed, target):
+        f, d, w = synth.training_batch(n, synth.rng_for(seed), target)
+        return torch.from_numpy(f).cuda(), torch.from_numpy(d).cuda(), torch.from_numpy(w).cuda()
+
+    vmf = synth.VmfTarget(4, seed=1001)
+    # C1: 9->64->64->64->8*4, FP32, 4096 vertices, one fwd+NLL+bwd+Adam step
+    g = guide(64, 3, 4, "f32", 4096)
+    b = batch(4096, 1000, vmf)
+    ms = kernel_avg_ms(lambda: g.train_step(*b), 50)
+    out["c1_fp32_step"] = {"us_per_step": round(ms * 1e3, 1), "batch": 4096}
+    del g, b
+    # C2: 9->64x4->8*8, FP32, 2^18 samples per step
+    n = 1 << 18
+    g = guide(64, 4, 8, "f32", n)
+    b = batch(n, 1001, vmf)
+    ms = kernel_avg_ms(lambda: g.train_step(*b), 10)
+    fl = train_flops(64, 4, 8) * n / (ms * 1e-3) / 1e12
+    out["c2_fp32_train"] = {"samples_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                            "mfma_tflops": round(fl, 2), "frac_fp32_mfma": round(fl / PEAK_F32_MFMA_TFLOPS, 4)}
+    del g, b
+    # C3: 9->64x4->8*16, 2^20 queries, BF16 and FP32 MLP
+    n = 1 << 20
+    rng = synth.rng_for(1002)
+    f = torch.from_numpy(synth.features(n, rng)).cuda()
+    xi = torch.from_numpy(synth.uniforms(n, rng)).cuda()
+    d, p = torch.empty(3, n, device="cuda"), torch.empty(n, device="cuda")
+    for prec in ("bf16", "f32"):
+        g = guide(64, 4, 16, prec, 1)
+        ms = kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p), 20)
+        out[f"c3_{prec}_query"] = {"queries_per_s": round(n / (ms * 1e-3), 1), "ms": round(ms, 4)}
+        del g
+    del f, xi, d, p
+    # C5: 9->128x4->8*32, BF16, 2^22 samples per step, anisotropic target
+    n = 1 << 22
+    g = guide(128, 4, 32, "bf16", n)
+    b = batch(n, 1004, synth.AnisoTarget(8, seed=1005))
+    ms = kernel_avg_ms(lambda: g.train_step(*b), 3)
+    fl = train_flops(128, 4, 32) * n / (ms * 1e-3) / 1e12
+    out["c5_bf16_train"] = {"samples_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 3),
+                            "mfma_tflops_algorithmic": round(fl, 1),
+                            "frac_bf16_mfma": round(fl / PEAK_BF16_TFLOPS, 4)}
+    del g, b
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(min_seconds=10.0, max_pieces=64, fraction=8):
     """The FP64 oracle on the host for a bounded sample of the frame: pieces
     of 1/fraction of a frame (every bounce's queries and the training samples
@@ -299,6 +372,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "steps": a.steps}))
         return
+    if a.only == "c5":
+        from paper_2303_08064_amd import synth
+        from paper_2303_08064_amd.nasg import NasgGuide
+        n = 1 << 22
+        mats = synth.init_weights(synth.layer_shapes(128, 4, 32), synth.rng_for(42))
+        g = NasgGuide(synth.flat_weights(mats), hidden=128, n_hidden=4, n_lobes=32, precision="bf16", max_batch=n)
+        f, d, w = synth.training_batch(n, synth.rng_for(1004), synth.AnisoTarget(8, seed=1005))
+        b = (torch.from_numpy(f).cuda(), torch.from_numpy(d).cuda(), torch.from_numpy(w).cuda())
+        for _ in range(a.steps):
+            g.train_step(*b)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "c5", "steps": a.steps}))
+        return
     if a.only == "records":
         print(json.dumps({"only": "records", **records_legs(frame, a.steps)}))
         return
@@ -328,6 +414,8 @@ def main():
         out["roofline"] = query_roofline(frame)
         out["records"] = records_legs(frame)
         out["train_step"] = train_leg(frame)
+    if not a.no_configs and a.only != "frame":
+        out["configs"] = config_legs()
     if not a.no_fp32 and a.only != "frame":
         f32 = Frame("f32")
         ms32, _ = time_frames(f32, max(5, a.steps // 5), 2, not a.no_graph)

@@ -14,7 +14,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnasg.so")
-SOURCES = ["query.hip", "records.hip", "train.hip", "api.hip"]
+SOURCES = ["query.hip", "records.hip", "train.hip", "large.hip", "api.hip"]
+# per-file code generation options: the query kernel keeps MFMA accumulators in
+# VGPRs (no accumulator-register reads in its VALU-bound epilogue); the
+# training kernel needs the accumulator registers for its gradient tiles
+EXTRA = {"query.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = os.environ.get("NASG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -32,7 +36,7 @@ def _hipcc():
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

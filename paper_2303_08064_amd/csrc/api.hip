@@ -34,6 +34,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool compiled(int H, int K, int prec) {
 #define NASG_CASE(h, k, p) if (H == h && K == k && prec == p) return true;
   NASG_FOR_EACH_NET(NASG_CASE)
+  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
+#undef NASG_CASE
+  return false;
+}
+
+bool is_large(int H, int K, int prec) {
+#define NASG_CASE(h, k, p) if (H == h && K == k && prec == p) return true;
+  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
 #undef NASG_CASE
   return false;
 }
@@ -45,18 +53,22 @@ const char* config_error(const nasg_config* c) {
   if (c->n_hidden < 1 || c->n_hidden > 4) return "n_hidden must be in 1..4";
   if (c->precision != NASG_F32 && c->precision != NASG_BF16) return "precision must be NASG_F32 or NASG_BF16";
   if (!compiled(c->hidden, c->n_lobes, c->precision))
-    return "unsupported (hidden, n_lobes, precision); compiled: hidden 64 with n_lobes 4, 8, 16";
+    return "unsupported (hidden, n_lobes, precision); compiled: hidden 64 with n_lobes 4, 8, 16 (FP32 or "
+           "BF16) and hidden 128 with n_lobes 32 (BF16)";
+  if (is_large(c->hidden, c->n_lobes, c->precision) && c->n_hidden != 4)
+    return "hidden 128 networks are compiled for n_hidden = 4";
   if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
   if (!(c->lr > 0.0f) || !isfinite(c->lr)) return "lr must be finite and > 0";
   if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
     return "beta1 and beta2 must be in [0, 1)";
   if (!(c->adam_eps > 0.0f) || !isfinite(c->adam_eps)) return "adam_eps must be finite and > 0";
   if (c->max_batch < 0) return "max_batch must be >= 0";
+  if (dims_of(c).num_weights() % 4 != 0) return "the weight count must be a multiple of 4";
   return nullptr;
 }
 
 struct Workspace {
-  size_t partial, loss_partial, norm_partial, step_snapshot, total;
+  size_t partial, loss_partial, norm_partial, step_snapshot, dout, total;
 };
 
 Workspace carve(const nasg_config* c) {
@@ -71,6 +83,12 @@ Workspace carve(const nasg_config* c) {
   off = align_up(off + (size_t)reduce_blocks(nw) * sizeof(double));
   w.step_snapshot = off;
   off = align_up(off + sizeof(int64_t));
+  w.dout = off;
+  if (is_large(c->hidden, c->n_lobes, c->precision)) {
+    // BF16 dL/d(raw outputs) of every sample of a training batch (64-vertex tiles)
+    const int64_t tiles = (c->max_batch + 63) / 64;
+    off = align_up(off + (size_t)tiles * 64 * 8 * c->n_lobes * 2);
+  }
   w.total = off;
   return w;
 }
@@ -212,7 +230,9 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.rec_out = rec_out;
   a.raw_out = raw_out;
   a.num_cus = ctx->num_cus;
-  hipError_t e = launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
+  hipError_t e = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)
+                     ? launch_large_query(a, ctx->d.H, ctx->d.K, mode, (hipStream_t)stream)
+                     : launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
@@ -309,7 +329,24 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   t.loss_partial = reinterpret_cast<double*>(ws + ctx->ws.loss_partial);
   t.n_weights = ctx->d.num_weights();
   t.num_cus = ctx->num_cus;
-  hipError_t e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
+  hipError_t e;
+  if (is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)) {
+    LargeTrainArgs la;
+    la.wpack = s.wpack;
+    la.eps = ctx->cfg.eps;
+    la.feat = feat;
+    la.dir = dir;
+    la.w = w;
+    la.ld = ld;
+    la.B = B;
+    la.dout = ws + ctx->ws.dout;
+    la.partial = t.partial;
+    la.loss_partial = t.loss_partial;
+    la.n_weights = t.n_weights;
+    e = launch_large_train(la, ctx->d.H, ctx->d.K, n_wg, (hipStream_t)stream);
+  } else {
+    e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(fn, e);
   ReduceArgs r;
   r.partial = t.partial;

@@ -1,0 +1,133 @@
+// MLP backward pieces shared by the training kernels: dgrad in registers,
+// staging of a layer's deltas and inputs for the weight gradient, the
+// weight-gradient MFMA over a workgroup's staged vertices, and the flush of a
+// wave's gradient tiles to its workgroup's partial.
+//
+// dW_l = sum_v delta_l(v) h_{l-1}(v)^T contracts over vertices, which sit in
+// different lanes of the accumulator layout, so the four waves of a
+// workgroup stage delta_l and h_{l-1} of its 64 vertices in LDS, and each
+// wave accumulates its own row tiles of dW_l.
+#pragma once
+
+#include "common.hpp"
+
+namespace nasg {
+
+constexpr int kWGV = 64;   // vertices per workgroup tile
+
+// delta_prev = W_l^T delta (contraction over the RT*16 rows of layer l),
+// rows of the result are the previous layer's neurons in accumulator layout.
+template <int H, int K, int PREC, int RT>
+__device__ __forceinline__ void dgrad(const void* wl, const float (&dl)[RT][4],
+                                      float (&dp)[H / 16][4], int lane) {
+  constexpr int MTP = H / 16;
+  if constexpr (PREC == 1) {
+    constexpr int KB = RT / 2;   // 32-wide blocks over the rows of layer l
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(wl);
+    bf16x8 b[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
+    }
+  } else {
+    const float* W = reinterpret_cast<const float*>(wl);
+    constexpr int P = H + 1;
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < 4 * RT; ++kb) {
+        // row R of layer l fed by slot (kb, g): accumulator dl[kb/4][kb%4]
+        const int R = (kb >> 2) * 16 + 4 * g + (kb & 3);
+        acc = mfma_f32_4(W[R * P + mt * 16 + c], dl[kb >> 2][kb & 3], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
+    }
+  }
+}
+
+// Write a wave's accumulator-layout block [RT*16 rows][16 vertices] into the
+// staging buffer at vertex column wave*16.
+template <typename S, int RT, int SP>
+__device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int wave, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) buf[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (S)x[mt][i];
+}
+
+// acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the 64 staged vertices
+template <int PREC, typename S, int SP, int NR, int NC>
+__device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const int (&rt)[NR], int nrt,
+                                            f32x4 (&acc)[NR][NC], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  if constexpr (PREC == 1) {
+#pragma unroll
+    for (int vb = 0; vb < kWGV / 32; ++vb) {
+      bf16x8 hb[NC];
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct)
+        hb[ct] = *reinterpret_cast<const bf16x8*>(hst + (ct * 16 + c) * SP + vb * 32 + 8 * g);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nrt) {
+          bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + (rt[r] * 16 + c) * SP + vb * 32 + 8 * g);
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_bf16_32(da, hb[ct], acc[r][ct]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int vb = 0; vb < kWGV / 4; ++vb) {
+      float hb[NC];
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct) hb[ct] = hst[(ct * 16 + c) * SP + vb * 4 + g];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nrt) {
+          float da = dst[(rt[r] * 16 + c) * SP + vb * 4 + g];
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_f32_4(da, hb[ct], acc[r][ct]);
+        }
+      }
+    }
+  }
+}
+
+// Flush a wave's dW tiles of layer l to the workgroup's canonical partial.
+template <int NR, int NC>
+__device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,
+                                            const f32x4 (&acc)[NR][NC], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  const int cols = d.cols(l);
+  const int64_t off = d.canon_off(l);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nrt) continue;
+#pragma unroll
+    for (int ct = 0; ct < NC; ++ct) {
+      const int k = ct * 16 + c;
+      if (k >= cols) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int R = rt[r] * 16 + 4 * g + i;
+        const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
+        part[off + (int64_t)n * cols + k] = acc[r][ct][i];
+      }
+    }
+  }
+}
+
+}  // namespace nasg

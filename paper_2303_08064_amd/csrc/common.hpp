@@ -47,6 +47,10 @@ __device__ __forceinline__ f32x4 mfma_f32_4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// max(x, 0) as one integer max on the bit pattern: negative floats (and -0)
+// are negative integers. Avoids the NaN canonicalisation fmaxf needs.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.0f, 0.0f, 0.0f, 0.0f}; }
 
 // Copy `bytes` (multiple of 16) from global to LDS with the whole block.

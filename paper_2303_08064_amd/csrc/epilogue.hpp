@@ -1,0 +1,144 @@
+// Per-vertex NASG epilogues on the MLP's output accumulators.
+//
+// `out[mt][i]` at lane (g, c) is raw output t = mt*4 + i of lobe
+// g*KQ + t % KQ, parameter t / KQ (layout.hpp), for vertex c. Each lane
+// handles KQ = K/4 lobes of one vertex; the four lanes c, c+16, c+32, c+48
+// together hold the K lobes.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace nasg {
+
+template <int KQ, int MTO>
+__device__ __forceinline__ void lobe_raw(const float (&out)[MTO][4], int q, float o[8]) {
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int t = p * KQ + q;
+    o[p] = out[t >> 2][t & 3];
+  }
+}
+
+// log-sum-exp of the K mixture logits (softmax of Tab. "decoding")
+template <int KQ, int MTO>
+__device__ __forceinline__ float logit_lse(const float (&out)[MTO][4]) {
+  float alpha[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int t = 7 * KQ + q;
+    alpha[q] = out[t >> 2][t & 3];
+  }
+  float mx = alpha[0];
+#pragma unroll
+  for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
+  mx = quad_max(mx);
+  float se = 0.0f;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
+  se = quad_sum(se);
+  return mx + flog(se);
+}
+
+// Weighted NLL of one vertex and its gradient w.r.t. the raw outputs
+// (Sec. 4.2): gs = dL/dlog q = -w/B (0 for padding lanes). Writes dl in the
+// accumulator layout and returns log q. For KQ > 4 the decode and the lobe
+// evaluation are recomputed in the backward loop instead of kept in
+// registers (the large network holds eight lobes per lane).
+template <int KQ, int MTO>
+__device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], float vx, float vy, float vz,
+                                                float gs, bool valid, float eps, float (&dl)[MTO][4]) {
+  const float lse = logit_lse<KQ, MTO>(out);
+  constexpr bool keep = KQ <= 4;
+  Lobe lb[keep ? KQ : 1];
+  LobeAux ax[keep ? KQ : 1];
+  Eval ev[keep ? KQ : 1];
+  float ell[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    float o[8];
+    lobe_raw<KQ, MTO>(out, q, o);
+    Lobe L;
+    LobeAux X;
+    decode_lobe(o, eps, L, X);
+    L.logc = (o[7] - lse) - X.logK;
+    Eval e = eval_lobe(L, vx, vy, vz, eps);
+    ell[q] = e.ell;
+    if constexpr (keep) { lb[q] = L; ax[q] = X; ev[q] = e; }
+  }
+  const float logq = mixture_lse<KQ>(ell);
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    float o[8];
+    lobe_raw<KQ, MTO>(out, q, o);
+    const float r = valid ? fexp(ell[q] - logq) : 0.0f;
+    const float Aq = fexp(o[7] - lse);
+    float gq[8];
+    if constexpr (keep) {
+      backward_lobe(lb[q], ax[q], ev[q], vx, vy, vz, eps, gs * r, gs * (r - Aq), gq);
+    } else {
+      Lobe L;
+      LobeAux X;
+      decode_lobe(o, eps, L, X);
+      L.logc = (o[7] - lse) - X.logK;
+      Eval e = eval_lobe(L, vx, vy, vz, eps);
+      backward_lobe(L, X, e, vx, vy, vz, eps, gs * r, gs * (r - Aq), gq);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int t = p * KQ + q;
+      dl[t >> 2][t & 3] = gq[p];
+    }
+  }
+  return logq;
+}
+
+// Guiding query of one vertex: decode, inverse-CDF lobe choice, App. C
+// sample, mixture pdf at the sample. Returns log q; v receives the unit
+// direction; lb receives the decoded lobes (for the optional record store).
+template <int KQ, int MTO>
+__device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], float xi_sel, float xi0, float xi1,
+                                                float xi2, float eps, int g, int c, Lobe (&lb)[KQ], float& vx,
+                                                float& vy, float& vz) {
+  float logK[KQ], alpha[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    float o[8];
+    lobe_raw<KQ, MTO>(out, q, o);
+    logK[q] = decode_lobe_query(o, eps, lb[q]);
+    alpha[q] = o[7];
+  }
+  // mixture weights: softmax over the K logits
+  float mx = alpha[0];
+#pragma unroll
+  for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
+  mx = quad_max(mx);
+  float ea[KQ];
+  float se = 0.0f;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    ea[q] = fexp(alpha[q] - mx);
+    se += ea[q];
+  }
+  se = quad_sum(se);
+  const float lse = mx + flog(se);
+  const float inv_se = frcp(se);
+  float A[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    lb[q].logc = (alpha[q] - lse) - logK[q];
+    A[q] = ea[q] * inv_se;
+  }
+  const int ksel = select_lobe<KQ>(A, xi_sel, g, c);
+  const Lobe s = broadcast_lobe<KQ>(lb, ksel, c);
+  sample_lobe(s, xi0, xi1, xi2, eps, vx, vy, vz);
+  const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+  vx *= inv;
+  vy *= inv;
+  vz *= inv;
+  float ell[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe(lb[q], vx, vy, vz, eps).ell;
+  return mixture_lse<KQ>(ell);
+}
+
+}  // namespace nasg

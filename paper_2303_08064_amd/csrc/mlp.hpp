@@ -53,7 +53,7 @@ struct Mlp<H, K, 1> {
     for (int mt = 0; mt < MTH; ++mt) {
       f32x4 acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(acc[i], 0.0f);
+      for (int i = 0; i < 4; ++i) h[mt][i] = relu(acc[i]);
     }
   }
 
@@ -112,7 +112,7 @@ struct Mlp<H, K, 0> {
 #pragma unroll
       for (int kb = 0; kb < 3; ++kb) acc = mfma_f32_4(lds[(mt * 16 + c) * P + kb * 4 + g], x.x[kb], acc);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[mt][i] = fmaxf(acc[i], 0.0f);
+      for (int i = 0; i < 4; ++i) h[mt][i] = relu(acc[i]);
     }
   }
 
@@ -171,7 +171,7 @@ struct Forward {
         for (int mt = 0; mt < M::MTH; ++mt)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            h[l][mt][i] = fmaxf(y[mt][i], 0.0f);
+            h[l][mt][i] = relu(y[mt][i]);
             last[mt][i] = h[l][mt][i];
           }
       }

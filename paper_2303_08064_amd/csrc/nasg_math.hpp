@@ -28,26 +28,22 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fsel(bool c, float a, float b) { return c ? a : b; }
 
-// e^x - 1, accurate in relative terms for |x| < 1/4 (Taylor series to x^7,
-// truncation below 2e-9 relative) and through exp elsewhere.
+// e^x - 1, accurate in relative terms: Taylor series to x^5 for |x| < 1/8
+// (truncation below 5e-8 relative), exp(x) - 1 elsewhere.
 __device__ __forceinline__ float expm1f_(float x) {
-  float p = fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
-  p = fmaf(x, p, 1.0f / 120.0f);
-  p = fmaf(x, p, 1.0f / 24.0f);
+  float p = fmaf(x, 1.0f / 120.0f, 1.0f / 24.0f);
   p = fmaf(x, p, 1.0f / 6.0f);
   p = fmaf(x, p, 0.5f);
   p = fmaf(x, p, 1.0f);
   p = p * x;
   float e = fexp(x) - 1.0f;
-  return fsel(fabsf(x) < 0.25f, p, e);
+  return fsel(fabsf(x) < 0.125f, p, e);
 }
 
-// log(1 + y) for y > -1, accurate in relative terms for |y| < 1/16 (series to
-// y^8, truncation below 2e-10 relative) and through log elsewhere.
+// log(1 + y) for y > -1, accurate in relative terms: series to y^6 for
+// |y| < 1/16 (truncation below 1e-8 relative), log(1 + y) elsewhere.
 __device__ __forceinline__ float log1pf_(float y) {
-  float p = fmaf(y, -1.0f / 8.0f, 1.0f / 7.0f);
-  p = fmaf(y, p, -1.0f / 6.0f);
-  p = fmaf(y, p, 1.0f / 5.0f);
+  float p = fmaf(y, -1.0f / 6.0f, 1.0f / 5.0f);
   p = fmaf(y, p, -1.0f / 4.0f);
   p = fmaf(y, p, 1.0f / 3.0f);
   p = fmaf(y, p, -0.5f);
@@ -135,6 +131,42 @@ __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L
   L.a = fexp(X.loga);
   X.logK = log_normaliser(L.lam, X.loglam, L.a, eps);
   L.logc = 0.0f;
+}
+
+// 1 - e^{-|o|}, accurate in relative terms (used where a pair of small raw
+// outputs is normalised, so their ratio must survive).
+__device__ __forceinline__ float one_minus_exp_neg(float ao) {
+  return -expm1f_(-ao);
+}
+
+// Forward-only decode for queries: the same function as decode_lobe, with
+// the sin/cos pairs normalised without reciprocals (a pair of tanh(o/2) =
+// m/(2 - m) values is scaled by (2 - m1)(2 - m2) > 0 before normalising) and
+// log K folded into log c by the caller. Returns log K.
+__device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, Lobe& L) {
+  // theta: cos = tanh(o0/2) (absolute accuracy suffices), sin = sech(o0/2)
+  const float e0 = fexp(-fabsf(o[0]));
+  const float r0 = frcp(1.0f + e0);
+  const float ct = copysignf((1.0f - e0) * r0, o[0]);
+  const float st = 2.0f * fsqrt(e0) * r0;
+  const float m1 = one_minus_exp_neg(fabsf(o[1])), m2 = one_minus_exp_neg(fabsf(o[2]));
+  const float m3 = one_minus_exp_neg(fabsf(o[3])), m4 = one_minus_exp_neg(fabsf(o[4]));
+  float cp, sp, ctau, stau, inv;
+  unit_pair(copysignf(m2 * (2.0f - m1), o[2]), copysignf(m1 * (2.0f - m2), o[1]), cp, sp, inv);
+  unit_pair(copysignf(m4 * (2.0f - m3), o[4]), copysignf(m3 * (2.0f - m4), o[3]), ctau, stau, inv);
+  L.zx = cp * st;
+  L.zy = sp * st;
+  L.zz = ct;
+  const float ctc = ct * ctau;
+  L.xx = fmaf(ctc, cp, -sp * stau);
+  L.xy = fmaf(ctc, sp, cp * stau);
+  L.xz = -st * ctau;
+  const float loglam = fminf(fmaxf(o[5], -kLogClamp), kLogClamp);
+  const float loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
+  L.lam = fexp(loglam);
+  L.a = fexp(loga);
+  L.logc = 0.0f;
+  return log_normaliser(L.lam, loglam, L.a, eps);
 }
 
 // Lobe value at a unit direction, with what the backward needs.

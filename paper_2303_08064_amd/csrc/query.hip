@@ -7,6 +7,7 @@
 // within-lane loop plus two cross-lane steps (xor 16, xor 32).
 #include <type_traits>
 
+#include "epilogue.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 
@@ -23,6 +24,7 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
   W* lds = reinterpret_cast<W*>(smem);
   block_copy_to_lds(lds, a.wpack, a.lds_bytes);
   __syncthreads();
+  const W* wts = lds;
 
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     float h[NHMAX][M::MTH][4];
     float last[M::MTH][4];
     float out[M::MTO][4];
-    F::run(lds, a.nh, x, h, last, out, lane);
+    F::run(wts, a.nh, x, h, last, out, lane);
 
     if (MODE == 1) {
       // raw outputs in canonical row order: accumulator t of lane group g is
@@ -50,41 +52,6 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
       continue;
     }
 
-    // ---- decode (Tab. "decoding", Euler frame of Sec. 4.1) ----
-    Lobe lb[KQ];
-    float logK[KQ], alpha[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      float o[8];
-#pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        int t = p * KQ + q;
-        o[p] = out[t >> 2][t & 3];
-      }
-      LobeAux aux;
-      decode_lobe(o, a.eps, lb[q], aux);
-      logK[q] = aux.logK;
-      alpha[q] = o[7];
-    }
-    // mixture weights: softmax over the K logits
-    float mx = alpha[0];
-#pragma unroll
-    for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
-    mx = quad_max(mx);
-    float se = 0.0f;
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
-    se = quad_sum(se);
-    const float lse = mx + flog(se);
-    float A[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      float logA = alpha[q] - lse;
-      lb[q].logc = logA - logK[q];
-      A[q] = fexp(logA);
-    }
-
-    // ---- inverse-CDF lobe choice over k = g*KQ + q ----
     float xi_sel = 0.0f, xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
     if (valid) {
       xi_sel = a.xi[v];
@@ -92,18 +59,9 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
       xi1 = a.xi[2 * a.ld + v];
       xi2 = a.xi[3 * a.ld + v];
     }
-    int ksel = select_lobe<KQ>(A, xi_sel, g, c);
-    Lobe s = broadcast_lobe<KQ>(lb, ksel, c);
-
-    // ---- sample (App. C) and evaluate the mixture there ----
+    Lobe lb[KQ];
     float vx, vy, vz;
-    sample_lobe(s, xi0, xi1, xi2, a.eps, vx, vy, vz);
-    float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
-    vx *= inv; vy *= inv; vz *= inv;
-    float ell[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe(lb[q], vx, vy, vz, a.eps).ell;
-    float logq = mixture_lse<KQ>(ell);
+    const float logq = query_epilogue<KQ, M::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz);
 
     if (valid && g == 0) {
       a.dir_out[v] = vx;

@@ -11,13 +11,14 @@
 // Every sum has a fixed order, so results are bitwise reproducible.
 #include <type_traits>
 
+#include "backward.hpp"
+#include "epilogue.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 
 namespace nasg {
 
 constexpr int kMaxTrainWG = 256;
-constexpr int kWGV = 64;   // vertices per workgroup tile
 
 template <int H, int K, int PREC>
 struct TrainCfg {
@@ -47,121 +48,6 @@ struct TrainLds {
     return lds + F32Layout{NetDims{H, nh, K}}.off(l);
   }
 };
-
-// delta_prev = W_l^T delta (contraction over the RT*16 rows of layer l),
-// rows of the result are the previous layer's neurons in accumulator layout.
-template <int H, int K, int PREC, int RT>
-__device__ __forceinline__ void dgrad(const void* wl, int rows_pitch_unused, const float (&dl)[RT][4],
-                                      float (&dp)[H / 16][4], int lane) {
-  constexpr int MTP = H / 16;
-  if constexpr (PREC == 1) {
-    constexpr int KB = RT / 2;   // 32-wide blocks over the rows of layer l
-    const bf16x8* frag = reinterpret_cast<const bf16x8*>(wl);
-    bf16x8 b[KB];
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) b[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
-#pragma unroll
-    for (int mt = 0; mt < MTP; ++mt) {
-      f32x4 acc = zero4();
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
-    }
-  } else {
-    const float* W = reinterpret_cast<const float*>(wl);
-    constexpr int P = H + 1;
-    const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-    for (int mt = 0; mt < MTP; ++mt) {
-      f32x4 acc = zero4();
-#pragma unroll
-      for (int kb = 0; kb < 4 * RT; ++kb) {
-        // row R of layer l fed by slot (kb, g): accumulator dl[kb/4][kb%4]
-        const int R = (kb >> 2) * 16 + 4 * g + (kb & 3);
-        acc = mfma_f32_4(W[R * P + mt * 16 + c], dl[kb >> 2][kb & 3], acc);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
-    }
-  }
-}
-
-// Write a wave's accumulator-layout block [RT*16 rows][16 vertices] into the
-// staging buffer at vertex column wave*16.
-template <typename S, int RT, int SP>
-__device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int wave, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) buf[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (S)x[mt][i];
-}
-
-// acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the 64 staged vertices
-template <int PREC, typename S, int SP, int NR, int NC>
-__device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const int (&rt)[NR], int nrt,
-                                            f32x4 (&acc)[NR][NC], int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  if constexpr (PREC == 1) {
-#pragma unroll
-    for (int vb = 0; vb < kWGV / 32; ++vb) {
-      bf16x8 hb[NC];
-#pragma unroll
-      for (int ct = 0; ct < NC; ++ct)
-        hb[ct] = *reinterpret_cast<const bf16x8*>(hst + (ct * 16 + c) * SP + vb * 32 + 8 * g);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (r < nrt) {
-          bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + (rt[r] * 16 + c) * SP + vb * 32 + 8 * g);
-#pragma unroll
-          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_bf16_32(da, hb[ct], acc[r][ct]);
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int vb = 0; vb < kWGV / 4; ++vb) {
-      float hb[NC];
-#pragma unroll
-      for (int ct = 0; ct < NC; ++ct) hb[ct] = hst[(ct * 16 + c) * SP + vb * 4 + g];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (r < nrt) {
-          float da = dst[(rt[r] * 16 + c) * SP + vb * 4 + g];
-#pragma unroll
-          for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_f32_4(da, hb[ct], acc[r][ct]);
-        }
-      }
-    }
-  }
-}
-
-// Flush a wave's dW tiles of layer l to the workgroup's canonical partial.
-template <int NR, int NC>
-__device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,
-                                            const f32x4 (&acc)[NR][NC], int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  const int cols = d.cols(l);
-  const int64_t off = d.canon_off(l);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (r >= nrt) continue;
-#pragma unroll
-    for (int ct = 0; ct < NC; ++ct) {
-      const int k = ct * 16 + c;
-      if (k >= cols) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int R = rt[r] * 16 + 4 * g + i;
-        const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-        part[off + (int64_t)n * cols + k] = acc[r][ct][i];
-      }
-    }
-  }
-}
 
 template <int H, int K, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -230,51 +116,12 @@ void train_kernel(TrainArgs a) {
       float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
     }
-    Lobe lb[KQ];
-    LobeAux ax[KQ];
-    float alpha[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      float o[8];
-#pragma unroll
-      for (int p = 0; p < 8; ++p) { const int t = p * KQ + q; o[p] = out[t >> 2][t & 3]; }
-      decode_lobe(o, a.eps, lb[q], ax[q]);
-      alpha[q] = o[7];
-    }
-    float mx = alpha[0];
-#pragma unroll
-    for (int q = 1; q < KQ; ++q) mx = fmaxf(mx, alpha[q]);
-    mx = quad_max(mx);
-    float se = 0.0f;
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
-    se = quad_sum(se);
-    const float lse = mx + flog(se);
-    float logA[KQ];
-    Eval ev[KQ];
-    float ell[KQ];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      logA[q] = alpha[q] - lse;
-      lb[q].logc = logA[q] - ax[q].logK;
-      ev[q] = eval_lobe(lb[q], vx, vy, vz, a.eps);
-      ell[q] = ev[q].ell;
-    }
-    const float logq = mixture_lse<KQ>(ell);
     const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q
+    float dl[MTO][4];
+    const float logq = train_epilogue<KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl);
     if (valid && g == 0) {
       loss_sum += (double)wj * (double)(-logq);
       w_sum += (double)wj;
-    }
-    float dl[MTO][4];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      const float r = valid ? fexp(ell[q] - logq) : 0.0f;
-      const float Aq = fexp(logA[q]);
-      float gq[8];
-      backward_lobe(lb[q], ax[q], ev[q], vx, vy, vz, a.eps, gs * r, gs * (r - Aq), gq);
-#pragma unroll
-      for (int p = 0; p < 8; ++p) { const int t = p * KQ + q; dl[t >> 2][t & 3] = gq[p]; }
     }
 
     // ---- MLP backward: output layer ----
@@ -282,7 +129,7 @@ void train_kernel(TrainArgs a) {
     {
       stage_rows<S, MTO, SP>(dst, dl, wave, lane);
       stage_rows<S, MTH, SP>(hst, last, wave, lane);
-      dgrad<H, K, PREC, MTO>(TL::bwd(lds, nh, nh), 0, dl, dh, lane);
+      dgrad<H, K, PREC, MTO>(TL::bwd(lds, nh, nh), dl, dh, lane);
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
@@ -303,7 +150,7 @@ void train_kernel(TrainArgs a) {
       stage_rows<S, MTH, SP>(dst, dh, wave, lane);
       stage_rows<S, MTH, SP>(hst, prev, wave, lane);
       float dn[MTH][4];
-      dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), 0, dh, dn, lane);
+      dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), dh, dn, lane);
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
@@ -389,20 +236,52 @@ hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hi
 }
 
 // ---------------------------------------------------------------- reduce ----
-// grad[i] = sum over workgroups (fixed order, FP64) of partial[wg][i];
-// per-block FP64 sums of grad^2; block 0 also totals the loss.
+// grad[i] = sum over workgroups of partial[wg][i] in a fixed order: thread
+// group q (of 16) of a block sums workgroups q, q+16, q+32, ... for four
+// consecutive weights with 16-byte loads (eight in flight, FP64 sums), then
+// the 16 group sums are added in order. Each block also writes its FP64 sum
+// of grad^2; block 0 totals the loss. n_weights is a multiple of 4 for every
+// compiled network (checked on the host).
+constexpr int kRedW = 64;   // weights per block
+constexpr int kRedQ = 16;   // workgroup groups per block
+
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double s = 0.0;
-  if (i < a.n_weights) {
-    for (int wg = 0; wg < a.n_wg; ++wg) s += (double)a.partial[(int64_t)wg * a.n_weights + i];
-    a.grad[i] = (float)s;
+  const int j = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * kRedW + 4 * j;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i0 < a.n_weights) {
+    const float* p = a.partial + i0;
+    int wg = q;
+    for (; wg + 7 * kRedQ < a.n_wg; wg += 8 * kRedQ) {
+      float4 x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const float4*>(p + (int64_t)(wg + u * kRedQ) * a.n_weights);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s[0] += (double)x[u].x; s[1] += (double)x[u].y; s[2] += (double)x[u].z; s[3] += (double)x[u].w;
+      }
+    }
+    for (; wg < a.n_wg; wg += kRedQ) {
+      const float4 x = *reinterpret_cast<const float4*>(p + (int64_t)wg * a.n_weights);
+      s[0] += (double)x.x; s[1] += (double)x.y; s[2] += (double)x.z; s[3] += (double)x.w;
+    }
   }
-  double gsq = i < a.n_weights ? (double)(float)s * (double)(float)s : 0.0;
-  __shared__ double red[256];
-  red[threadIdx.x] = gsq;
+  __shared__ double part[kRedQ][kRedW];
+  __shared__ double red[kRedW];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) part[q][4 * j + u] = s[u];
   __syncthreads();
-  for (int k = 128; k >= 1; k >>= 1) {
+  if (threadIdx.x < kRedW) {
+    const int64_t i = (int64_t)blockIdx.x * kRedW + threadIdx.x;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedQ; ++k) t += part[k][threadIdx.x];
+    const float gf = (float)t;
+    if (i < a.n_weights) a.grad[i] = gf;
+    red[threadIdx.x] = i < a.n_weights ? (double)gf * (double)gf : 0.0;
+  }
+  __syncthreads();
+  for (int k = kRedW / 2; k >= 1; k >>= 1) {
     if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
@@ -417,7 +296,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   }
 }
 
-int reduce_blocks(int64_t n_weights) { return (int)((n_weights + 255) / 256); }
+int reduce_blocks(int64_t n_weights) { return (int)((n_weights + kRedW - 1) / kRedW); }
 
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(n_blocks), dim3(256), 0, st, a);

@@ -13,6 +13,7 @@ CONFIGS = {
     "c3_f32": (64, 4, 16, "f32"),
     "c2_bf16": (64, 4, 8, "bf16"),
     "c1_bf16": (64, 3, 4, "bf16"),
+    "c5_bf16": (128, 4, 32, "bf16"),
 }
 
 

@@ -69,7 +69,7 @@ def test_forward_raw_f32(name):
     assert err.max() < 1e-5, err.max()
 
 
-@pytest.mark.parametrize("name", ["c1_bf16", "c2_bf16", "c3_bf16"])
+@pytest.mark.parametrize("name", ["c1_bf16", "c2_bf16", "c3_bf16", "c5_bf16"])
 def test_forward_raw_bf16(name):
     """Against the oracle's BF16 emulation: 99.9% of outputs within 1e-4 of the
     row's max magnitude, all within 2e-2 (a hidden activation whose FP32 sum
@@ -124,7 +124,7 @@ def test_query_f32(name, scale):
     assert np.abs(np.log(pdf) - lq2)[ok].max() < 1e-3
 
 
-@pytest.mark.parametrize("name", ["c3_bf16", "c2_bf16"])
+@pytest.mark.parametrize("name", ["c3_bf16", "c2_bf16", "c5_bf16"])
 def test_query_bf16(name):
     """BF16 MLP, FP32 NASG: against the BF16-emulating oracle, |d log q| median
     <= 1e-3 and p99 <= 1e-2 at the sampled directions; against the pure FP64
@@ -145,7 +145,7 @@ def test_query_bf16(name):
     assert err2.max() < 1e-4
 
 
-@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16"])
 def test_pdf_kernel(name):
     """nasg_pdf on records at sampled, target-like and uniform directions."""
     K = CONFIGS[name][2]
@@ -165,7 +165,7 @@ def test_pdf_kernel(name):
         assert np.abs(np.log(pg) - lq)[ok].max() < 1e-4
 
 
-@pytest.mark.parametrize("name", ["c1_f32", "c3_bf16"])
+@pytest.mark.parametrize("name", ["c1_f32", "c3_bf16", "c5_bf16"])
 def test_sample_kernel(name):
     """nasg_sample on records: same lobe rule and App. C map as the oracle."""
     K = CONFIGS[name][2]
@@ -233,7 +233,7 @@ def test_loss_grad_f32(name, B, seed):
     assert max(errs_e2e) < 1e-3, errs_e2e
 
 
-@pytest.mark.parametrize("name", ["c3_bf16", "c2_bf16"])
+@pytest.mark.parametrize("name", ["c3_bf16", "c2_bf16", "c5_bf16"])
 def test_loss_grad_bf16(name):
     """BF16 operands (weights, activations, backward deltas) with FP32
     accumulation vs the oracle's BF16-emulated forward differentiated in FP64:
@@ -256,7 +256,7 @@ def test_loss_grad_bf16(name):
     assert max(errs_e2e) < 5e-2, errs_e2e
 
 
-@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16"])
 def test_adam_step_and_repacked_weights(name):
     """Adam (Kingma and Ba) from the GPU gradient vs the oracle's update; then
     the kernels must see the new weights (the packed copy is refreshed)."""
@@ -307,7 +307,7 @@ def test_adam_skips_non_finite():
     assert not torch.equal(g.w, before)
 
 
-@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16"])
 def test_training_is_deterministic(name):
     outs = []
     for _ in range(2):
