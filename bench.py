@@ -159,15 +159,19 @@ QUERY_SOURCES = ["query.hip", "mlp.hpp", "nasg_math.hpp", "common.hpp", "kernels
 
 def committed_traffic():
     """HBM bytes per query launch from the committed counter summary, if it was
-    taken on the current query-kernel sources."""
-    p = os.path.join(ROOT, "profiles", "query_bf16_k16_1m_counters.json")
+    taken on the current query-kernel sources (its `source_hash:` line)."""
+    p = os.path.join(ROOT, "profiles", "query_bf16_k16_1m_counters.txt")
     if not os.path.exists(p):
         return None
+    fields = {}
     with open(p) as f:
-        d = json.load(f)
-    if d.get("source_hash") != source_hash(QUERY_SOURCES):
+        for line in f:
+            key, sep, val = line.partition(":")
+            if sep and key.strip() in ("source_hash", "hbm_bytes_per_launch"):
+                fields[key.strip()] = val.strip()
+    if fields.get("source_hash") != source_hash(QUERY_SOURCES) or "hbm_bytes_per_launch" not in fields:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return int(fields["hbm_bytes_per_launch"])
 
 
 def query_roofline(frame, reps=20):
@@ -281,16 +285,19 @@ def config_legs():
         out[f"c3_{prec}_query"] = {"queries_per_s": round(n / (ms * 1e-3), 1), "ms": round(ms, 4)}
         del g
     del f, xi, d, p
-    # C5: 9->128x4->8*32, BF16, 2^22 samples per step, anisotropic target
+    # C5: 9->128x4->8*32, 2^22 samples per step, anisotropic target; BF16
+    # (the configuration's precision) and FP32 (its comparison)
     n = 1 << 22
-    g = guide(128, 4, 32, "bf16", n)
     b = batch(n, 1004, synth.AnisoTarget(8, seed=1005))
-    ms = kernel_avg_ms(lambda: g.train_step(*b), 3)
-    fl = train_flops(128, 4, 32) * n / (ms * 1e-3) / 1e12
-    out["c5_bf16_train"] = {"samples_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 3),
-                            "mfma_tflops_algorithmic": round(fl, 1),
-                            "frac_bf16_mfma": round(fl / PEAK_BF16_TFLOPS, 4)}
-    del g, b
+    for prec, peak in (("bf16", PEAK_BF16_TFLOPS), ("f32", PEAK_F32_MFMA_TFLOPS)):
+        g = guide(128, 4, 32, prec, n)
+        ms = kernel_avg_ms(lambda: g.train_step(*b), 3 if prec == "bf16" else 1)
+        fl = train_flops(128, 4, 32) * n / (ms * 1e-3) / 1e12
+        out[f"c5_{prec}_train"] = {"samples_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 3),
+                                   "mfma_tflops_algorithmic": round(fl, 1),
+                                   f"frac_{prec}_mfma": round(fl / peak, 4)}
+        del g
+    del b
     torch.cuda.synchronize()
     return out
 

@@ -53,8 +53,8 @@ const char* config_error(const nasg_config* c) {
   if (c->n_hidden < 1 || c->n_hidden > 4) return "n_hidden must be in 1..4";
   if (c->precision != NASG_F32 && c->precision != NASG_BF16) return "precision must be NASG_F32 or NASG_BF16";
   if (!compiled(c->hidden, c->n_lobes, c->precision))
-    return "unsupported (hidden, n_lobes, precision); compiled: hidden 64 with n_lobes 4, 8, 16 (FP32 or "
-           "BF16) and hidden 128 with n_lobes 32 (BF16)";
+    return "unsupported (hidden, n_lobes); compiled: hidden 64 with n_lobes 4, 8, 16 and hidden 128 with "
+           "n_lobes 32, each in FP32 or BF16";
   if (is_large(c->hidden, c->n_lobes, c->precision) && c->n_hidden != 4)
     return "hidden 128 networks are compiled for n_hidden = 4";
   if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
@@ -85,9 +85,11 @@ Workspace carve(const nasg_config* c) {
   off = align_up(off + sizeof(int64_t));
   w.dout = off;
   if (is_large(c->hidden, c->n_lobes, c->precision)) {
-    // BF16 dL/d(raw outputs) of every sample of a training batch (64-vertex tiles)
+    // dL/d(raw outputs) of every sample of a training batch (64-vertex tiles),
+    // BF16 or FP32 as the network
     const int64_t tiles = (c->max_batch + 63) / 64;
-    off = align_up(off + (size_t)tiles * 64 * 8 * c->n_lobes * 2);
+    const size_t elem = c->precision == NASG_BF16 ? 2 : 4;
+    off = align_up(off + (size_t)tiles * 64 * 8 * c->n_lobes * elem);
   }
   w.total = off;
   return w;
@@ -231,7 +233,7 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.raw_out = raw_out;
   a.num_cus = ctx->num_cus;
   hipError_t e = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)
-                     ? launch_large_query(a, ctx->d.H, ctx->d.K, mode, (hipStream_t)stream)
+                     ? launch_large_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream)
                      : launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
@@ -343,7 +345,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.partial = t.partial;
     la.loss_partial = t.loss_partial;
     la.n_weights = t.n_weights;
-    e = launch_large_train(la, ctx->d.H, ctx->d.K, n_wg, (hipStream_t)stream);
+    e = launch_large_train(la, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
   } else {
     e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
   }

@@ -9,9 +9,10 @@
 // Network shapes with compiled kernels: (hidden width, lobes, precision).
 #define NASG_FOR_EACH_NET(X) \
   X(64, 4, 0) X(64, 4, 1) X(64, 8, 0) X(64, 8, 1) X(64, 16, 0) X(64, 16, 1)
-// Large networks (BF16, 4 hidden layers): weights stream through LDS a layer
-// at a time and training runs as separate NASG-gradient and backward kernels.
-#define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 1)
+// Large networks (4 hidden layers): weights stream through LDS while the
+// workgroup moves through the layers, and training runs as separate
+// NASG-gradient and backward kernels.
+#define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0) X(128, 32, 1)
 
 namespace nasg {
 
@@ -62,7 +63,8 @@ struct LargeTrainArgs {
   const float* dir;
   const float* w;
   int64_t ld, B;
-  void* dout;            // dL/d(raw outputs), BF16 operand image, 16 B x K/4 x 64 per 16 vertices
+  void* dout;            // dL/d(raw outputs) per 16 vertices: BF16 operand image (16 B x K/4 x 64)
+                         // or FP32 accumulator image (16 B x K/2 x 64)
   float* partial;        // [n_wg][n_weights]
   double* loss_partial;  // [n_wg][2]
   int64_t n_weights;
@@ -165,8 +167,8 @@ hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hi
 hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
-hipError_t launch_large_query(const QueryArgs& a, int H, int K, int mode, hipStream_t st);
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int n_wg, hipStream_t st);
+hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
+hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st);

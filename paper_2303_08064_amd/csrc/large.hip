@@ -1,80 +1,242 @@
-// Large networks (hidden 128, K = 32, BF16): query and training.
+// Large networks (hidden 128, K = 32): query and training, BF16 and FP32.
 //
-// The BF16 forward fragments of this network take 164 KiB and the backward
-// ones another 160 KiB, more than one CU's 160 KiB of LDS, and its 83,200
-// FP32 weight-gradient accumulators would need ~325 registers per lane in
-// each of four waves. So:
-// * weights stream through one 64 KiB LDS buffer a layer at a time (the
-//   workgroup moves through the layers together, 64 vertices per tile);
+// This network's forward weights alone (164 KiB in BF16) exceed one CU's
+// 160 KiB of LDS, and its 83,200 FP32 weight-gradient accumulators would need
+// ~325 registers per lane in each of four waves. So:
+// * weights stream through an LDS buffer while the workgroup moves through
+//   the layers together (64 vertices per tile): a whole layer at a time in
+//   BF16 (at most 64 KiB of MFMA fragments), 64 rows at a time in FP32
+//   (33 KiB of the row-major layout);
 // * training runs as three kernels over the batch: gradout_kernel does the
 //   forward and the weighted-NLL / NASG backward (Sec. 4.2) and keeps only
-//   dL/d(raw outputs) as BF16 (512 B per sample, the operand image the
-//   backward reads); bwd_kernel<0> and bwd_kernel<1> each recompute the
-//   forward, run dgrad and accumulate the weight gradient of one group of
-//   layers (the output and last hidden layer; the rest) in registers.
-//   Activations are recomputed, never stored.
+//   dL/d(raw outputs) (the operand image the backward reads: 512 B per
+//   sample in BF16, 1 KiB in FP32); bwd_kernel<0> and bwd_kernel<1> each
+//   recompute the forward, run dgrad and accumulate the weight gradient of one
+//   group of layers (the output and last hidden layer; the rest) in
+//   registers. Activations are recomputed, never stored.
 #include <type_traits>
 
+#include "backward.hpp"
 #include "epilogue.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 
 namespace nasg {
 
-constexpr int kLargeWGV = 64;   // vertices per workgroup tile
-
-template <int H, int K>
+template <int H, int K, int PREC>
 struct LargeNet {
-  typedef Mlp<H, K, 1> M;
+  typedef Mlp<H, K, PREC> M;
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
   static constexpr int NH = 4;
   static constexpr int MTH = H / 16, MTO = K / 2, KQ = K / 4;
-  static constexpr int KBO = K / 4;                         // 32-wide blocks over the 8K outputs
-  static constexpr int BUF_ELEMS = (8 * K * H > H * H) ? 8 * K * H : H * H;   // largest layer
-  static constexpr int SP = kLargeWGV + 8;                  // staging pitch (bf16)
+  static constexpr int CH = 64;              // FP32 rows per LDS chunk
+  static constexpr int TPC = CH / 16;        // FP32 row tiles per chunk
+  static constexpr int PH = H + 1;           // FP32 pitch of hidden and output layers
+  static constexpr int P0 = kInPadded + 1;   // FP32 pitch of layer 0
+  static constexpr int BUF_ELEMS = PREC == 1 ? ((8 * K * H > H * H) ? 8 * K * H : H * H)
+                                             : ((CH * PH > H * P0) ? CH * PH : H * P0);
+  static constexpr int SP = PREC == 1 ? kWGV + 8 : kWGV + 4;   // staging pitch
   static constexpr int RMAX = 8 * K;
 
   // Replace the LDS weight buffer's contents (whole workgroup).
-  __device__ static void wstage(__bf16* buf, const __bf16* src, int elems) {
+  __device__ static void wstage(W* buf, const W* src, int elems) {
     __syncthreads();
-    block_copy_to_lds(buf, src, elems * 2);
+    block_copy_to_lds(buf, src, elems * (int)sizeof(W));
     __syncthreads();
   }
 
-  __device__ static void forward(const __bf16* wg, __bf16* buf, const typename M::Input& x,
-                                 float (&h)[NH][MTH][4], float (&out)[MTO][4], int lane) {
-    const Bf16Layout Lt{NetDims{H, NH, K}};
-    wstage(buf, wg + Lt.fwd_off(0), H * 16);
+  // y = W_l h over all MT_*16 rows of layer l, streaming the weights
+  template <int MT_>
+  __device__ static void layer(const W* wg, W* buf, int l, const float (&in)[MTH][4], float (&y)[MT_][4],
+                               int lane) {
+    if constexpr (PREC == 1) {
+      const Bf16Layout Lt{NetDims{H, NH, K}};
+      wstage(buf, wg + Lt.fwd_off(l), MT_ * 16 * H);
+      M::template gemm<MT_>(buf, in, y, lane);
+    } else {
+      const F32Layout Lt{NetDims{H, NH, K}};
+#pragma unroll
+      for (int ch = 0; ch < MT_ / TPC; ++ch) {
+        wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
+        float part[TPC][4];
+        M::template gemm<TPC>(buf, in, part, lane);   // rows ch*CH .. ch*CH + CH - 1
+#pragma unroll
+        for (int t = 0; t < TPC; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) y[ch * TPC + t][i] = part[t][i];
+      }
+    }
+  }
+
+  __device__ static void forward(const W* wg, W* buf, const typename M::Input& x, float (&h)[NH][MTH][4],
+                                 float (&out)[MTO][4], int lane) {
+    if constexpr (PREC == 1) {
+      wstage(buf, wg + Bf16Layout{NetDims{H, NH, K}}.fwd_off(0), H * 16);
+    } else {
+      wstage(buf, wg + F32Layout{NetDims{H, NH, K}}.off(0), H * P0);
+    }
     M::layer0(buf, x, h[0], lane);
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
-      wstage(buf, wg + Lt.fwd_off(l), H * H);
       float y[MTH][4];
-      M::template gemm<MTH>(buf, h[l - 1], y, lane);
+      layer<MTH>(wg, buf, l, h[l - 1], y, lane);
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) h[l][mt][i] = relu(y[mt][i]);
     }
-    wstage(buf, wg + Lt.fwd_off(NH), 8 * K * H);
-    M::template gemm<MTO>(buf, h[NH - 1], out, lane);
+    layer<MTO>(wg, buf, NH, h[NH - 1], out, lane);
+  }
+
+  // dp = W_l^T dl (rows of layer l = RT*16), streaming the backward weights
+  template <int RT>
+  __device__ static void dgrad_layer(const W* wg, W* buf, int l, const float (&dl)[RT][4], float (&dp)[MTH][4],
+                                     int lane) {
+    if constexpr (PREC == 1) {
+      const Bf16Layout Lt{NetDims{H, NH, K}};
+      wstage(buf, wg + Lt.bwd_off(l), RT * 16 * H);
+      dgrad<H, K, 1, RT>(buf, dl, dp, lane);
+    } else {
+      const F32Layout Lt{NetDims{H, NH, K}};
+      const int g = lane >> 4, c = lane & 15;
+      f32x4 acc[MTH];
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt) acc[mt] = zero4();
+      // slot (kb, g) of the contraction is row (kb/4)*16 + 4g + kb%4 of layer l,
+      // held in dl[kb/4][kb%4]; chunk ch holds rows [CH*ch, CH*ch + CH)
+#pragma unroll
+      for (int ch = 0; ch < RT / TPC; ++ch) {
+        wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+          for (int kk = 0; kk < 4 * TPC; ++kk) {
+            const int kb = 4 * TPC * ch + kk;
+            const int r = ((kb >> 2) - TPC * ch) * 16 + 4 * g + (kb & 3);
+            acc[mt] = mfma_f32_4(buf[r * PH + mt * 16 + c], dl[kb >> 2][kb & 3], acc[mt]);
+          }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dp[mt][i] = acc[mt][i];
+    }
+  }
+};
+
+// Hidden activations kept by the backward kernels: BF16 pairs for the BF16
+// network (used only as BF16 staging operands and as ReLU masks h > 0),
+// FP32 otherwise.
+template <int PREC, int MTH>
+struct Act;
+
+template <int MTH>
+struct Act<1, MTH> {
+  uint32_t p[MTH][2];
+  __device__ void set(const float (&h)[MTH][4]) {
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t lo = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k]);
+        const uint32_t hi = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k + 1]);
+        p[mt][k] = lo | (hi << 16);
+      }
+  }
+  __device__ float get(int mt, int i) const {
+    const uint32_t w = p[mt][i >> 1];
+    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+};
+
+template <int MTH>
+struct Act<0, MTH> {
+  float v[MTH][4];
+  __device__ void set(const float (&h)[MTH][4]) {
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[mt][i] = h[mt][i];
+  }
+  __device__ float get(int mt, int i) const { return v[mt][i]; }
+};
+
+template <int PREC, int MTH>
+__device__ __forceinline__ void mask_relu(float (&d)[MTH][4], const Act<PREC, MTH>& h) {
+#pragma unroll
+  for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[mt][i] = h.get(mt, i) > 0.0f ? d[mt][i] : 0.0f;
+}
+
+template <typename S, int PREC, int MTH, int SP>
+__device__ __forceinline__ void stage_act(S* st, const Act<PREC, MTH>& h, int wave, int lane) {
+  float x[MTH][4];
+#pragma unroll
+  for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[mt][i] = h.get(mt, i);
+  stage_rows<S, MTH, SP>(st, x, wave, lane);
+}
+
+// dL/d(raw outputs) of 16 vertices: BF16 as the output layer's dgrad B
+// operands (K/4 16-byte slots per lane); FP32 as the accumulator image
+// (K/2 16-byte slots per lane).
+template <int K, int PREC>
+struct DOut {
+  static constexpr int MTO = K / 2, KBO = K / 4;
+  __device__ static void store(void* base, int64_t tile16, const float (&dl)[MTO][4], int lane) {
+    if constexpr (PREC == 1) {
+      bf16x8* d = reinterpret_cast<bf16x8*>(base) + tile16 * KBO * 64 + lane;
+#pragma unroll
+      for (int kb = 0; kb < KBO; ++kb) {
+        bf16x8 b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
+        d[kb * 64] = b;
+      }
+    } else {
+      float4* d = reinterpret_cast<float4*>(base) + tile16 * MTO * 64 + lane;
+#pragma unroll
+      for (int mt = 0; mt < MTO; ++mt) d[mt * 64] = float4{dl[mt][0], dl[mt][1], dl[mt][2], dl[mt][3]};
+    }
+  }
+  __device__ static void load(const void* base, int64_t tile16, float (&dl)[MTO][4], int lane) {
+    if constexpr (PREC == 1) {
+      const bf16x8* s = reinterpret_cast<const bf16x8*>(base) + tile16 * KBO * 64 + lane;
+#pragma unroll
+      for (int kb = 0; kb < KBO; ++kb) {
+        const bf16x8 b = s[kb * 64];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dl[2 * kb + (j >> 2)][j & 3] = (float)b[j];
+      }
+    } else {
+      const float4* s = reinterpret_cast<const float4*>(base) + tile16 * MTO * 64 + lane;
+#pragma unroll
+      for (int mt = 0; mt < MTO; ++mt) {
+        const float4 x = s[mt * 64];
+        dl[mt][0] = x.x; dl[mt][1] = x.y; dl[mt][2] = x.z; dl[mt][3] = x.w;
+      }
+    }
   }
 };
 
 // ---------------------------------------------------------------- query ----
-template <int H, int K, int MODE>
+template <int H, int K, int PREC, int MODE>
 __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
-  typedef LargeNet<H, K> N;
+  typedef LargeNet<H, K, PREC> N;
   typedef typename N::M M;
+  typedef typename N::W W;
   constexpr int KQ = N::KQ;
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* buf = reinterpret_cast<__bf16*>(smem);
-  const __bf16* wg = reinterpret_cast<const __bf16*>(a.wpack);
+  W* buf = reinterpret_cast<W*>(smem);
+  const W* wg = reinterpret_cast<const W*>(a.wpack);
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
-  const int64_t n_tiles = (a.B + kLargeWGV - 1) / kLargeWGV;
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t v = tile * kLargeWGV + wave * 16 + c;
+    const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
     float h[N::NH][N::MTH][4];
@@ -121,22 +283,23 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
 }
 
 // ------------------------------------------------------------- gradient ----
-template <int H, int K>
+template <int H, int K, int PREC>
 __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
-  typedef LargeNet<H, K> N;
+  typedef LargeNet<H, K, PREC> N;
   typedef typename N::M M;
-  constexpr int KQ = N::KQ, MTO = N::MTO, KBO = N::KBO;
+  typedef typename N::W W;
+  constexpr int KQ = N::KQ, MTO = N::MTO;
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* buf = reinterpret_cast<__bf16*>(smem);
-  const __bf16* wg = reinterpret_cast<const __bf16*>(a.wpack);
+  W* buf = reinterpret_cast<W*>(smem);
+  const W* wg = reinterpret_cast<const W*>(a.wpack);
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
   const float inv_b = 1.0f / (float)a.B;
   double loss_sum = 0.0, w_sum = 0.0;
-  const int64_t n_tiles = (a.B + kLargeWGV - 1) / kLargeWGV;
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t v = tile * kLargeWGV + wave * 16 + c;
+    const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
     float h[N::NH][N::MTH][4];
@@ -156,15 +319,7 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
       loss_sum += (double)wj * (double)(-logq);
       w_sum += (double)wj;
     }
-    // the output layer's dgrad B operands, one 16-byte slot per lane and block
-    bf16x8* dst = reinterpret_cast<bf16x8*>(a.dout) + ((tile * 4 + wave) * KBO) * 64 + lane;
-#pragma unroll
-    for (int kb = 0; kb < KBO; ++kb) {
-      bf16x8 b;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) b[j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
-      dst[kb * 64] = b;
-    }
+    DOut<K, PREC>::store(a.dout, tile * 4 + wave, dl, lane);
   }
   __shared__ double red[4][2];
 #pragma unroll
@@ -181,134 +336,22 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
 }
 
 // ------------------------------------------------------------- backward ----
-// dgrad with W_l^T fragments in LDS (contraction over RT row tiles of layer l)
-template <int H, int RT>
-__device__ __forceinline__ void dgrad_bf16(const __bf16* wl, const float (&dl)[RT][4], float (&dp)[H / 16][4],
-                                           int lane) {
-  constexpr int KB = RT / 2;
-  const bf16x8* frag = reinterpret_cast<const bf16x8*>(wl);
-  bf16x8 b[KB];
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) b[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
-#pragma unroll
-  for (int mt = 0; mt < H / 16; ++mt) {
-    f32x4 acc = zero4();
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
-  }
-}
-
-template <int RT, int SP>
-__device__ __forceinline__ void stage_bf16(__bf16* st, const float (&x)[RT][4], int wave, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int mt = 0; mt < RT; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) st[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (__bf16)x[mt][i];
-}
-
-// acc[r][ct] += D[row tile rt[r]][64 staged vertices] * Hs[col tile ct][...]^T
-template <int SP, int NR, int NC>
-__device__ __forceinline__ void wgrad_bf16(const __bf16* dst, const __bf16* hst, const int (&rt)[NR], int nrt,
-                                           f32x4 (&acc)[NR][NC], int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int vb = 0; vb < kLargeWGV / 32; ++vb) {
-    bf16x8 hb[NC];
-#pragma unroll
-    for (int ct = 0; ct < NC; ++ct)
-      hb[ct] = *reinterpret_cast<const bf16x8*>(hst + (ct * 16 + c) * SP + vb * 32 + 8 * g);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r < nrt) {
-        const bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + (rt[r] * 16 + c) * SP + vb * 32 + 8 * g);
-#pragma unroll
-        for (int ct = 0; ct < NC; ++ct) acc[r][ct] = mfma_bf16_32(da, hb[ct], acc[r][ct]);
-      }
-    }
-  }
-}
-
-template <int NR, int NC>
-__device__ __forceinline__ void flush_bf16(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,
-                                           const f32x4 (&acc)[NR][NC], int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  const int cols = d.cols(l);
-  const int64_t off = d.canon_off(l);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (r >= nrt) continue;
-#pragma unroll
-    for (int ct = 0; ct < NC; ++ct) {
-      const int k = ct * 16 + c;
-      if (k >= cols) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int R = rt[r] * 16 + 4 * g + i;
-        const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-        part[off + (int64_t)n * cols + k] = acc[r][ct][i];
-      }
-    }
-  }
-}
-
-// Hidden activations kept as bfloat16 pairs: the backward uses them only as
-// BF16 staging operands and as ReLU masks (h > 0).
-template <int MTH>
-struct PackedAct {
-  uint32_t p[MTH][2];
-  __device__ void pack(const float (&h)[MTH][4]) {
-#pragma unroll
-    for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const uint32_t lo = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k]);
-        const uint32_t hi = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k + 1]);
-        p[mt][k] = lo | (hi << 16);
-      }
-  }
-  __device__ float get(int mt, int i) const {
-    const uint32_t w = p[mt][i >> 1];
-    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
-  }
-};
-
-template <int MTH>
-__device__ __forceinline__ void mask_relu(float (&d)[MTH][4], const PackedAct<MTH>& h) {
-#pragma unroll
-  for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[mt][i] = h.get(mt, i) > 0.0f ? d[mt][i] : 0.0f;
-}
-
-template <int MTH, int SP>
-__device__ __forceinline__ void stage_packed(__bf16* st, const PackedAct<MTH>& h, int wave, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) st[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (__bf16)h.get(mt, i);
-}
-
 // GROUP 0: weight gradients of the output layer and the last hidden layer;
 // GROUP 1: of hidden layers NH-2 .. 1 and layer 0.
-template <int H, int K, int GROUP>
+template <int H, int K, int PREC, int GROUP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void bwd_kernel(LargeTrainArgs a) {
-  typedef LargeNet<H, K> N;
+  typedef LargeNet<H, K, PREC> N;
   typedef typename N::M M;
-  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, KBO = N::KBO, SP = N::SP;
+  typedef typename N::W W;
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type S;
+  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, SP = N::SP;
   constexpr int RTW_H = (MTH + 3) / 4, RTW_O = (MTO + 3) / 4, CTH = H / 16;
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* buf = reinterpret_cast<__bf16*>(smem);
-  __bf16* dst = buf + N::BUF_ELEMS;
-  __bf16* hst = dst + N::RMAX * SP;
-  const __bf16* wg = reinterpret_cast<const __bf16*>(a.wpack);
-  const Bf16Layout Lt{NetDims{H, NH, K}};
+  W* buf = reinterpret_cast<W*>(smem);
+  S* dst = reinterpret_cast<S*>(smem + N::BUF_ELEMS * sizeof(W));
+  S* hst = dst + N::RMAX * SP;
+  const W* wg = reinterpret_cast<const W*>(a.wpack);
   const NetDims dims{H, NH, K};
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
@@ -321,12 +364,12 @@ void bwd_kernel(LargeTrainArgs a) {
 #pragma unroll
   for (int r = 0; r < RTW_O; ++r) { rt_o[r] = wave + 4 * r; if (rt_o[r] < MTO) nrt_o = r + 1; }
 
-  // GROUP 0: accA = output layer [RTW_O][CTH], accB = layer NH-1 [RTW_H][CTH]
-  // GROUP 1: accA = layers NH-2..1 [NH-2][RTW_H][CTH], accB = layer 0 [RTW_H][1]
-  f32x4 accO[GROUP == 0 ? RTW_O : 1][CTH];
-  f32x4 accT[RTW_H][CTH];
-  f32x4 accM[GROUP == 1 ? NH - 2 : 1][RTW_H][CTH];
-  f32x4 acc0[RTW_H][1];
+  constexpr int NO = GROUP == 0 ? RTW_O : 1;        // output layer (group 0)
+  constexpr int NM = GROUP == 1 ? NH - 2 : 1;       // hidden layers NH-2..1 (group 1)
+  f32x4 accO[NO][CTH];
+  f32x4 accT[RTW_H][CTH];                           // layer NH-1 (group 0)
+  f32x4 accM[NM][RTW_H][CTH];
+  f32x4 acc0[RTW_H][1];                             // layer 0 (group 1)
 #pragma unroll
   for (int r = 0; r < RTW_H; ++r) {
     acc0[r][0] = zero4();
@@ -334,76 +377,63 @@ void bwd_kernel(LargeTrainArgs a) {
     for (int ct = 0; ct < CTH; ++ct) {
       accT[r][ct] = zero4();
 #pragma unroll
-      for (int l = 0; l < (GROUP == 1 ? NH - 2 : 1); ++l) accM[l][r][ct] = zero4();
+      for (int l = 0; l < NM; ++l) accM[l][r][ct] = zero4();
     }
   }
 #pragma unroll
-  for (int r = 0; r < (GROUP == 0 ? RTW_O : 1); ++r)
+  for (int r = 0; r < NO; ++r)
 #pragma unroll
     for (int ct = 0; ct < CTH; ++ct) accO[r][ct] = zero4();
 
-  const int64_t n_tiles = (a.B + kLargeWGV - 1) / kLargeWGV;
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t v = tile * kLargeWGV + wave * 16 + c;
+    const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    PackedAct<MTH> hp[NH];
+    Act<PREC, MTH> hp[NH];
     {
       float h[NH][MTH][4];
       float out[MTO][4];
       N::forward(wg, buf, x, h, out, lane);
 #pragma unroll
-      for (int l = 0; l < NH; ++l) hp[l].pack(h[l]);
+      for (int l = 0; l < NH; ++l) hp[l].set(h[l]);
     }
-    // dL/d(raw outputs) from gradout_kernel, back in accumulator layout
     float dl[MTO][4];
-    {
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(a.dout) + ((tile * 4 + wave) * KBO) * 64 + lane;
-#pragma unroll
-      for (int kb = 0; kb < KBO; ++kb) {
-        const bf16x8 b = src[kb * 64];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dl[2 * kb + (j >> 2)][j & 3] = (float)b[j];
-      }
-    }
+    DOut<K, PREC>::load(a.dout, tile * 4 + wave, dl, lane);
     float dh[MTH][4];
     if constexpr (GROUP == 0) {
-      stage_bf16<MTO, SP>(dst, dl, wave, lane);
-      stage_packed<MTH, SP>(hst, hp[NH - 1], wave, lane);
-      N::wstage(buf, wg + Lt.bwd_off(NH), 8 * K * H);   // also publishes the staging
-      dgrad_bf16<H, MTO>(buf, dl, dh, lane);
-      mask_relu<MTH>(dh, hp[NH - 1]);
-      wgrad_bf16<SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
+      stage_rows<S, MTO, SP>(dst, dl, wave, lane);
+      stage_act<S, PREC, MTH, SP>(hst, hp[NH - 1], wave, lane);
+      N::template dgrad_layer<MTO>(wg, buf, NH, dl, dh, lane);   // its weight staging publishes the above
+      mask_relu<PREC, MTH>(dh, hp[NH - 1]);
+      wgrad_tiles<PREC, S, SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
       __syncthreads();
-      stage_bf16<MTH, SP>(dst, dh, wave, lane);
-      stage_packed<MTH, SP>(hst, hp[NH - 2], wave, lane);
+      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
+      stage_act<S, PREC, MTH, SP>(hst, hp[NH - 2], wave, lane);
       __syncthreads();
-      wgrad_bf16<SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
+      wgrad_tiles<PREC, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
       __syncthreads();
     } else {
-      N::wstage(buf, wg + Lt.bwd_off(NH), 8 * K * H);
-      dgrad_bf16<H, MTO>(buf, dl, dh, lane);
-      mask_relu<MTH>(dh, hp[NH - 1]);
+      N::template dgrad_layer<MTO>(wg, buf, NH, dl, dh, lane);
+      mask_relu<PREC, MTH>(dh, hp[NH - 1]);
       float d2[MTH][4];
-      N::wstage(buf, wg + Lt.bwd_off(NH - 1), H * H);
-      dgrad_bf16<H, MTH>(buf, dh, d2, lane);
-      mask_relu<MTH>(d2, hp[NH - 2]);
+      N::template dgrad_layer<MTH>(wg, buf, NH - 1, dh, d2, lane);
+      mask_relu<PREC, MTH>(d2, hp[NH - 2]);
 #pragma unroll
       for (int l = NH - 2; l >= 1; --l) {
-        stage_bf16<MTH, SP>(dst, d2, wave, lane);
-        stage_packed<MTH, SP>(hst, hp[l - 1], wave, lane);
-        N::wstage(buf, wg + Lt.bwd_off(l), H * H);
+        stage_rows<S, MTH, SP>(dst, d2, wave, lane);
+        stage_act<S, PREC, MTH, SP>(hst, hp[l - 1], wave, lane);
         float dn[MTH][4];
-        dgrad_bf16<H, MTH>(buf, d2, dn, lane);
-        mask_relu<MTH>(dn, hp[l - 1]);
-        wgrad_bf16<SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
+        N::template dgrad_layer<MTH>(wg, buf, l, d2, dn, lane);   // publishes the staging
+        mask_relu<PREC, MTH>(dn, hp[l - 1]);
+        wgrad_tiles<PREC, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
         __syncthreads();
 #pragma unroll
         for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
           for (int i = 0; i < 4; ++i) d2[mt][i] = dn[mt][i];
       }
-      stage_bf16<MTH, SP>(dst, d2, wave, lane);
+      stage_rows<S, MTH, SP>(dst, d2, wave, lane);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 4 * g + j;
@@ -412,22 +442,22 @@ void bwd_kernel(LargeTrainArgs a) {
           if (k < kInFeatures) xv = a.feat[(int64_t)k * a.ld + v];
           else if (k == kInFeatures) xv = 1.0f;
         }
-        hst[k * SP + wave * 16 + c] = (__bf16)xv;
+        hst[k * SP + wave * 16 + c] = (S)xv;
       }
       __syncthreads();
-      wgrad_bf16<SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      wgrad_tiles<PREC, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
       __syncthreads();
     }
   }
 
   float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
   if constexpr (GROUP == 0) {
-    flush_bf16<RTW_O, CTH>(part, dims, NH, rt_o, nrt_o, accO, lane);
-    flush_bf16<RTW_H, CTH>(part, dims, NH - 1, rt_h, nrt_h, accT, lane);
+    flush_tiles<RTW_O, CTH>(part, dims, NH, rt_o, nrt_o, accO, lane);
+    flush_tiles<RTW_H, CTH>(part, dims, NH - 1, rt_h, nrt_h, accT, lane);
   } else {
 #pragma unroll
-    for (int l = 1; l <= NH - 2; ++l) flush_bf16<RTW_H, CTH>(part, dims, l, rt_h, nrt_h, accM[l - 1], lane);
-    flush_bf16<RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
+    for (int l = 1; l <= NH - 2; ++l) flush_tiles<RTW_H, CTH>(part, dims, l, rt_h, nrt_h, accM[l - 1], lane);
+    flush_tiles<RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
   }
 }
 
@@ -437,56 +467,60 @@ static hipError_t set_lds(Kern kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int H, int K>
+template <int H, int K, int PREC>
 static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t st) {
-  typedef LargeNet<H, K> N;
-  const size_t shmem = (size_t)N::BUF_ELEMS * 2;
-  auto kern = mode == 0 ? large_query_kernel<H, K, 0> : large_query_kernel<H, K, 1>;
+  typedef LargeNet<H, K, PREC> N;
+  const size_t shmem = (size_t)N::BUF_ELEMS * sizeof(typename N::W);
+  auto kern = mode == 0 ? large_query_kernel<H, K, PREC, 0> : large_query_kernel<H, K, PREC, 1>;
   static bool attr[2] = {false, false};
   if (!attr[mode]) {
     hipError_t e = set_lds(kern, shmem);
     if (e != hipSuccess) return e;
     attr[mode] = true;
   }
-  const int64_t n_tiles = (a.B + kLargeWGV - 1) / kLargeWGV;
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   const int64_t cap = 2LL * a.num_cus;
   const int grid = (int)(n_tiles < cap ? (n_tiles < 1 ? 1 : n_tiles) : cap);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), shmem, st, a);
   return hipGetLastError();
 }
 
-template <int H, int K>
+template <int H, int K, int PREC>
 static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, hipStream_t st) {
-  typedef LargeNet<H, K> N;
-  const size_t sh_fwd = (size_t)N::BUF_ELEMS * 2;
-  const size_t sh_bwd = sh_fwd + (size_t)(N::RMAX + H) * N::SP * 2;
+  typedef LargeNet<H, K, PREC> N;
+  typedef typename std::conditional<PREC == 1, __bf16, float>::type S;
+  const size_t sh_fwd = (size_t)N::BUF_ELEMS * sizeof(typename N::W);
+  const size_t sh_bwd = sh_fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(S);
+  auto k_grad = gradout_kernel<H, K, PREC>;
+  auto k_bwd0 = bwd_kernel<H, K, PREC, 0>;
+  auto k_bwd1 = bwd_kernel<H, K, PREC, 1>;
   static bool attr = false;
   if (!attr) {
-    auto k_grad = gradout_kernel<H, K>;
-    auto k_bwd0 = bwd_kernel<H, K, 0>;
-    auto k_bwd1 = bwd_kernel<H, K, 1>;
     hipError_t e = set_lds(k_grad, sh_fwd);
     if (e == hipSuccess) e = set_lds(k_bwd0, sh_bwd);
     if (e == hipSuccess) e = set_lds(k_bwd1, sh_bwd);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  auto k_grad = gradout_kernel<H, K>;
-  auto k_bwd0 = bwd_kernel<H, K, 0>;
-  auto k_bwd1 = bwd_kernel<H, K, 1>;
   hipLaunchKernelGGL(k_grad, dim3(n_wg), dim3(256), sh_fwd, st, a);
   hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(256), sh_bwd, st, a);
   hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(256), sh_bwd, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_large_query(const QueryArgs& a, int H, int K, int mode, hipStream_t st) {
-  if (H == 128 && K == 32) return launch_large_query_t<128, 32>(a, mode, st);
+hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st) {
+#define NASG_CASE(h, k, p) \
+  if (H == h && K == k && prec == p) return launch_large_query_t<h, k, p>(a, mode, st);
+  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
+#undef NASG_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int n_wg, hipStream_t st) {
-  if (H == 128 && K == 32) return launch_large_train_t<128, 32>(a, n_wg, st);
+hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st) {
+#define NASG_CASE(h, k, p) \
+  if (H == h && K == k && prec == p) return launch_large_train_t<h, k, p>(a, n_wg, st);
+  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
+#undef NASG_CASE
   return hipErrorInvalidValue;
 }
 

@@ -14,6 +14,7 @@ CONFIGS = {
     "c2_bf16": (64, 4, 8, "bf16"),
     "c1_bf16": (64, 3, 4, "bf16"),
     "c5_bf16": (128, 4, 32, "bf16"),
+    "c5_f32": (128, 4, 32, "f32"),
 }
 
 

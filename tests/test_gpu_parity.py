@@ -59,7 +59,7 @@ def cdf_margin(lobes, xi_sel):
     return torch.abs(C - torch.as_tensor(xi_sel, dtype=F64)[:, None]).min(-1).values.numpy()
 
 
-@pytest.mark.parametrize("name", ["c1_f32", "c2_f32", "c3_f32"])
+@pytest.mark.parametrize("name", ["c1_f32", "c2_f32", "c3_f32", "c5_f32"])
 def test_forward_raw_f32(name):
     g, mats = make_guide(name, out_scale=3.0)
     feat, _ = inputs(B_RAGGED, 1)
@@ -89,7 +89,7 @@ def _gpu_lobes(g, feat, K):
     return onasg.decode(torch.tensor(raw), K)
 
 
-@pytest.mark.parametrize("name", ["c1_f32", "c2_f32", "c3_f32"])
+@pytest.mark.parametrize("name", ["c1_f32", "c2_f32", "c3_f32", "c5_f32"])
 @pytest.mark.parametrize("scale", [1.0, 3.0])
 def test_query_f32(name, scale):
     K = CONFIGS[name][2]
@@ -106,8 +106,11 @@ def test_query_f32(name, scale):
     assert (np.abs(recg[..., 6:8] - ro[..., 6:8]) / ro[..., 6:8]).max() < 1e-5
     assert np.abs(recg[..., 8] - ro[..., 8]).max() < 1e-5
     # end to end from the features: same records within FP32 MLP rounding
+    # carried through the frame angles (an angle from a (cos, sin) pair of
+    # norm r moves by |d pair| / r; theta's sine by cot(theta) |d cos|), the
+    # same conditioning as the end-to-end pdf bound below
     lob_e2e = onasg.decode(omlp.forward(w64(mats), feat.T), K)
-    assert np.abs(recg[..., 0:6] - lob_e2e.record().numpy()[..., 0:6]).max() < 1e-4
+    assert np.abs(recg[..., 0:6] - lob_e2e.record().numpy()[..., 0:6]).max() < 1e-3
     # sampled direction
     vo, _ = onasg.sample(lob, xi.T.astype(np.float64))
     vo = vo.numpy()
@@ -210,7 +213,7 @@ def _rel_errors(gpu_list, ref_list):
 
 
 @pytest.mark.parametrize("name,B,seed", [("c1_f32", 4096, 10), ("c2_f32", B_RAGGED, 10),
-                                         ("c2_f32", 4096, 3), ("c3_f32", 777, 10)])
+                                         ("c2_f32", 4096, 3), ("c3_f32", 777, 10), ("c5_f32", 777, 10)])
 def test_loss_grad_f32(name, B, seed):
     K = CONFIGS[name][2]
     g, mats = make_guide(name, out_scale=2.0)
@@ -256,7 +259,7 @@ def test_loss_grad_bf16(name):
     assert max(errs_e2e) < 5e-2, errs_e2e
 
 
-@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16"])
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16", "c5_f32"])
 def test_adam_step_and_repacked_weights(name):
     """Adam (Kingma and Ba) from the GPU gradient vs the oracle's update; then
     the kernels must see the new weights (the packed copy is refreshed)."""
@@ -307,7 +310,7 @@ def test_adam_skips_non_finite():
     assert not torch.equal(g.w, before)
 
 
-@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16"])
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16", "c5_f32"])
 def test_training_is_deterministic(name):
     outs = []
     for _ in range(2):

@@ -64,12 +64,14 @@ def test_size_queries(lib):
     # unsupported configurations report zero sizes
     assert lib.nasg_packed_bytes(ctypes.byref(_cfg(hidden=48))) == 0
     assert lib.nasg_workspace_bytes(ctypes.byref(_cfg(n_lobes=5))) == 0
-    # the large network: BF16 only, 4 hidden layers; its workspace holds the
-    # BF16 raw-output gradient of a whole batch (512 B per sample at K = 32)
+    # the large network: 4 hidden layers; its workspace holds the raw-output
+    # gradient of a whole batch (512 B per sample at K = 32 in BF16, 1 KiB in FP32)
     big = _cfg(hidden=128, n_lobes=32, max_batch=1 << 12)
     assert lib.nasg_num_weights(ctypes.byref(big)) == 83200
     assert lib.nasg_workspace_bytes(ctypes.byref(big)) >= 256 * 83200 * 4 + (1 << 12) * 512
-    assert lib.nasg_packed_bytes(ctypes.byref(_cfg(hidden=128, n_lobes=32, precision=0))) == 0
+    big32 = _cfg(hidden=128, n_lobes=32, precision=0, max_batch=1 << 12)
+    assert lib.nasg_workspace_bytes(ctypes.byref(big32)) >= 256 * 83200 * 4 + (1 << 12) * 1024
+    assert lib.nasg_packed_bytes(ctypes.byref(big32)) == 4 * (128 * 17 + 3 * 128 * 129 + 256 * 129)
     assert lib.nasg_packed_bytes(ctypes.byref(_cfg(hidden=128, n_lobes=32, n_hidden=3))) == 0
 
 
