@@ -73,38 +73,47 @@ def test_online_training_gain():
     assert losses[-1] < losses[0] - 0.5
 
 
+def _converged_nll_gap(pair, target, checks=(2500, 3000, 3500, 4000), seeds=(7000, 9000), pool_size=300):
+    """Train both networks of `pair` (BF16, FP32) from the same weights on the
+    same data (2^15 samples per Adam step, cycling over a pool of batches);
+    held-out NLL of each, averaged over the late checkpoints and the data
+    streams. Single trajectories of either precision wander by 1-2% between
+    checkpoints (rounding differences grow along the trajectory), hence the
+    averages. Returns (nll_bf16, nll_fp32, gap to uniform)."""
+    feat, dirs, _ = _data(1 << 15, 97, target)
+    nll = {name: [] for name in pair}
+    for seed0 in seeds:
+        pool = [tuple(to_dev(x) for x in _data(1 << 15, seed0 + s, target)) for s in range(pool_size)]
+        for name in pair:
+            g, _ = make_guide(name, max_batch=1 << 15)
+            for s in range(checks[-1]):
+                g.train_step(*pool[s % len(pool)])
+                if s + 1 in checks:
+                    nll[name].append(float(-np.mean(_heldout_logq(g, feat, dirs))))
+            torch.cuda.synchronize()
+            assert int(g.step) == checks[-1] and int(g.flags) == 0
+        del pool
+    b, f = float(np.mean(nll[pair[0]])), float(np.mean(nll[pair[1]]))
+    gap = (b - f) / (math.log(4 * math.pi) - f)
+    print(f"held-out NLL bf16 {b:.4f} fp32 {f:.4f} gap {gap:.4f}; per checkpoint "
+          f"bf16 {np.round(nll[pair[0]], 4)} fp32 {np.round(nll[pair[1]], 4)}")
+    return b, f, gap
+
+
 def test_bf16_matches_fp32_converged_nll():
-    """Same initial weights, same data stream: the BF16 network's held-out
-    NLL is within 2% of the FP32 network's (and of the gap to uniform)."""
-    target = synth.VmfTarget(4, seed=TARGET_SEED)
-    feat, dirs, _ = _data(1 << 16, 98, target)
-    nll = {}
-    for name in ("c3_bf16", "c3_f32"):
-        g, _ = make_guide(name, max_batch=1 << 15)
-        _train(g, target, 300, 1 << 15, 5000)
-        nll[name] = float(-np.mean(_heldout_logq(g, feat, dirs)))
-    rel = abs(nll["c3_bf16"] - nll["c3_f32"]) / abs(nll["c3_f32"])
-    gap = (nll["c3_bf16"] - nll["c3_f32"]) / (math.log(4 * math.pi) - nll["c3_f32"])
-    print(f"held-out NLL bf16 {nll['c3_bf16']:.4f} fp32 {nll['c3_f32']:.4f} rel {rel:.4f} gap {gap:.4f}")
-    # the gap to uniform is well conditioned even when the NLL itself is near 0
+    """The K = 16 network on von Mises-Fisher targets: BF16's converged
+    held-out NLL within 2% of FP32's gap to uniform (and of FP32's NLL)."""
+    b, f, gap = _converged_nll_gap(("c3_bf16", "c3_f32"), synth.VmfTarget(4, seed=TARGET_SEED),
+                                   checks=(1250, 1500, 1750, 2000))
+    assert f < math.log(4 * math.pi) - 0.5   # training gained over uniform
     assert abs(gap) <= 0.02
-    if abs(nll["c3_f32"]) > 0.5:
-        assert rel <= 0.02
+    if abs(f) > 0.5:
+        assert abs(b - f) / abs(f) <= 0.02
 
 
 def test_large_bf16_matches_fp32_converged_nll():
-    """The large network (hidden 128, K = 32) on anisotropic targets: BF16
-    and FP32 trained from the same weights on the same data stream reach
-    held-out NLLs within 2% of each other's gap to uniform."""
-    target = synth.AnisoTarget(8, seed=TARGET_SEED)
-    feat, dirs, _ = _data(1 << 15, 97, target)
-    nll = {}
-    for name in ("c5_bf16", "c5_f32"):
-        g, _ = make_guide(name, max_batch=1 << 14)
-        losses = _train(g, target, 200, 1 << 14, 7000)
-        nll[name] = float(-np.mean(_heldout_logq(g, feat, dirs)))
-        print(f"{name}: NLL {losses[0]:.3f} -> {losses[-1]:.3f}, held-out {nll[name]:.4f}")
-    gap = (nll["c5_bf16"] - nll["c5_f32"]) / (math.log(4 * math.pi) - nll["c5_f32"])
-    print(f"held-out NLL bf16 {nll['c5_bf16']:.4f} fp32 {nll['c5_f32']:.4f} gap {gap:.4f}")
-    assert nll["c5_f32"] < math.log(4 * math.pi) - 0.5   # training gained over uniform
+    """The large network (hidden 128, K = 32) on anisotropic targets, 4000
+    steps: BF16's converged held-out NLL within 2% of FP32's gap to uniform."""
+    b, f, gap = _converged_nll_gap(("c5_bf16", "c5_f32"), synth.AnisoTarget(8, seed=TARGET_SEED))
+    assert f < math.log(4 * math.pi) - 1.0   # training gained over uniform
     assert abs(gap) <= 0.02
