@@ -26,7 +26,6 @@ nasg_status hip_fail(const char* fn, hipError_t e) {
   return NASG_E_HIP;
 }
 
-constexpr int kMaxTrainWG = 256;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -78,7 +77,7 @@ Workspace carve(const nasg_config* c) {
   w.partial = off;
   off = align_up(off + (size_t)kMaxTrainWG * nw * sizeof(float));
   w.loss_partial = off;
-  off = align_up(off + (size_t)kMaxTrainWG * 2 * sizeof(double));
+  off = align_up(off + (size_t)2 * kMaxTrainWG * 2 * sizeof(double));
   w.norm_partial = off;
   off = align_up(off + (size_t)reduce_blocks(nw) * sizeof(double));
   w.step_snapshot = off;
@@ -317,6 +316,8 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   const nasg_state& s = ctx->st;
   unsigned char* ws = static_cast<unsigned char*>(s.workspace);
   const int n_wg = train_workgroups(B, ctx->num_cus);
+  const bool large = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision);
+  const int n_loss = large ? gradout_workgroups(B, ctx->num_cus) : n_wg;
   TrainArgs t;
   t.wpack = s.wpack;
   t.lds_bytes = (int)packed_bytes_of(&ctx->cfg);
@@ -332,7 +333,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   t.n_weights = ctx->d.num_weights();
   t.num_cus = ctx->num_cus;
   hipError_t e;
-  if (is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)) {
+  if (large) {
     LargeTrainArgs la;
     la.wpack = s.wpack;
     la.eps = ctx->cfg.eps;
@@ -345,7 +346,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.partial = t.partial;
     la.loss_partial = t.loss_partial;
     la.n_weights = t.n_weights;
-    e = launch_large_train(la, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
+    e = launch_large_train(la, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, n_loss, (hipStream_t)stream);
   } else {
     e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
   }
@@ -354,6 +355,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   r.partial = t.partial;
   r.loss_partial = t.loss_partial;
   r.n_wg = n_wg;
+  r.n_loss = n_loss;
   r.n_weights = t.n_weights;
   r.B = B;
   r.grad = s.grad;

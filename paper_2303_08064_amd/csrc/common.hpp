@@ -61,4 +61,28 @@ __device__ __forceinline__ void block_copy_to_lds(void* lds, const void* src, in
   for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
 
+// Asynchronous copy of `bytes` (multiple of 16) from global memory to LDS
+// with the whole block, through the gfx950 direct-to-LDS load
+// (global_load_lds_dwordx4): every wave moves 1 KiB per instruction, lane i
+// landing at LDS offset 16 i of that KiB, without passing through registers.
+// All loads are issued before any completes; lds_dma_wait() then waits for
+// this wave's copies, and a barrier after it publishes everyone's.
+__device__ __forceinline__ void lds_dma(void* lds, const void* src, int bytes) {
+  const int wave = (int)(threadIdx.x >> 6), lane = lane_id();
+  const int nw = (int)(blockDim.x >> 6);
+  const int chunks = (bytes + 1023) >> 10;
+  for (int j = wave; j < chunks; j += nw) {
+    const int off = j * 1024 + lane * 16;
+    if (off < bytes)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(src) + off,
+                                       (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(lds) +
+                                                                                 j * 1024),
+                                       16, 0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(0): every vector-memory load of this wave, including the
+// direct-to-LDS copies, has completed (expcnt and lgkmcnt left unconstrained).
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 }  // namespace nasg

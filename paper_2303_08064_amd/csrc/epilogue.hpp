@@ -41,17 +41,18 @@ __device__ __forceinline__ float logit_lse(const float (&out)[MTO][4]) {
 
 // Weighted NLL of one vertex and its gradient w.r.t. the raw outputs
 // (Sec. 4.2): gs = dL/dlog q = -w/B (0 for padding lanes). Writes dl in the
-// accumulator layout and returns log q. For KQ > 4 the decode and the lobe
-// evaluation are recomputed in the backward loop instead of kept in
-// registers (the large network holds eight lobes per lane).
+// accumulator layout and returns log q.
+//
+// One pass over the lobes: each lobe is decoded and evaluated once, and its
+// log-density's partials d ell_k / d o_p (p < 7) go straight into dl. They
+// are linear in the upstream factor, which is only known once log q is:
+// dL/d o_p = gs r_k d ell_k / d o_p with r_k = q_k / q, and for the logit
+// dL/d o_7 = gs (r_k - A_k) (through the softmax). A second, cheap loop
+// scales them.
 template <int KQ, int MTO>
 __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], float vx, float vy, float vz,
                                                 float gs, bool valid, float eps, float (&dl)[MTO][4]) {
   const float lse = logit_lse<KQ, MTO>(out);
-  constexpr bool keep = KQ <= 4;
-  Lobe lb[keep ? KQ : 1];
-  LobeAux ax[keep ? KQ : 1];
-  Eval ev[keep ? KQ : 1];
   float ell[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
@@ -61,33 +62,29 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
     LobeAux X;
     decode_lobe(o, eps, L, X);
     L.logc = (o[7] - lse) - X.logK;
-    Eval e = eval_lobe(L, vx, vy, vz, eps);
+    const Eval e = eval_lobe(L, vx, vy, vz, eps);
     ell[q] = e.ell;
-    if constexpr (keep) { lb[q] = L; ax[q] = X; ev[q] = e; }
+    float gq[8];
+    backward_lobe(L, X, e, vx, vy, vz, eps, 1.0f, 0.0f, gq);
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      const int t = p * KQ + q;
+      dl[t >> 2][t & 3] = gq[p];
+    }
   }
   const float logq = mixture_lse<KQ>(ell);
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
-    float o[8];
-    lobe_raw<KQ, MTO>(out, q, o);
+    const int t7 = 7 * KQ + q;
     const float r = valid ? fexp(ell[q] - logq) : 0.0f;
-    const float Aq = fexp(o[7] - lse);
-    float gq[8];
-    if constexpr (keep) {
-      backward_lobe(lb[q], ax[q], ev[q], vx, vy, vz, eps, gs * r, gs * (r - Aq), gq);
-    } else {
-      Lobe L;
-      LobeAux X;
-      decode_lobe(o, eps, L, X);
-      L.logc = (o[7] - lse) - X.logK;
-      Eval e = eval_lobe(L, vx, vy, vz, eps);
-      backward_lobe(L, X, e, vx, vy, vz, eps, gs * r, gs * (r - Aq), gq);
-    }
+    const float Aq = fexp(out[t7 >> 2][t7 & 3] - lse);
+    const float sc = gs * r;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
+    for (int p = 0; p < 7; ++p) {
       const int t = p * KQ + q;
-      dl[t >> 2][t & 3] = gq[p];
+      dl[t >> 2][t & 3] = fsel(sc == 0.0f, 0.0f, dl[t >> 2][t & 3] * sc);   // no 0 * inf
     }
+    dl[t7 >> 2][t7 & 3] = gs * (r - Aq);
   }
   return logq;
 }

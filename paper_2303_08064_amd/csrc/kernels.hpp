@@ -65,15 +65,16 @@ struct LargeTrainArgs {
   int64_t ld, B;
   void* dout;            // dL/d(raw outputs) per 16 vertices: BF16 operand image (16 B x K/4 x 64)
                          // or FP32 accumulator image (16 B x K/2 x 64)
-  float* partial;        // [n_wg][n_weights]
-  double* loss_partial;  // [n_wg][2]
+  float* partial;        // [n_wg][n_weights] (backward kernels' grid)
+  double* loss_partial;  // [n_grad][2] (gradient kernel's grid)
   int64_t n_weights;
 };
 
 struct ReduceArgs {
   const float* partial;
   const double* loss_partial;
-  int n_wg;
+  int n_wg;              // dW partials
+  int n_loss;            // loss partial pairs
   int64_t n_weights;
   int64_t B;
   float* grad;
@@ -168,14 +169,18 @@ hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
 hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
+hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, int n_grad,
+                              hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st);
 hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st);
 
 // Query / train kernel grid bounds (workgroups) for a batch of B vertices.
+constexpr int kMaxTrainWG = 256;
 int train_workgroups(int64_t B, int num_cus);
+// the large network's gradient kernel: up to two workgroups per CU
+int gradout_workgroups(int64_t B, int num_cus);
 int reduce_blocks(int64_t n_weights);
 
 }  // namespace nasg

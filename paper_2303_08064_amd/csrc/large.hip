@@ -3,16 +3,18 @@
 // This network's forward weights alone (164 KiB in BF16) exceed one CU's
 // 160 KiB of LDS, and its 83,200 FP32 weight-gradient accumulators would need
 // ~325 registers per lane in each of four waves. So:
-// * weights stream through an LDS buffer while the workgroup moves through
-//   the layers together (64 vertices per tile): a whole layer at a time in
-//   BF16 (at most 64 KiB of MFMA fragments), 64 rows at a time in FP32
-//   (33 KiB of the row-major layout);
+// * weights stream through LDS while the workgroup moves through the layers
+//   together (64 vertices per tile). BF16: two 32 KiB buffers in a pipeline;
+//   each stage is one layer of MFMA fragments (the output layer in two
+//   halves), and while the waves compute from one buffer the next stage
+//   arrives in the other by asynchronous direct-to-LDS loads. FP32 (the
+//   comparison path): one buffer, 64 rows (33 KiB) at a time.
 // * training runs as three kernels over the batch: gradout_kernel does the
 //   forward and the weighted-NLL / NASG backward (Sec. 4.2) and keeps only
 //   dL/d(raw outputs) (the operand image the backward reads: 512 B per
-//   sample in BF16, 1 KiB in FP32); bwd_kernel<0> and bwd_kernel<1> each
-//   recompute the forward, run dgrad and accumulate the weight gradient of one
-//   group of layers (the output and last hidden layer; the rest) in
+//   sample in BF16, 1 KiB in FP32); the two backward kernels each recompute
+//   the forward, run dgrad and accumulate the weight gradient of one group of
+//   layers (group 0: the output and last hidden layer; group 1: the rest) in
 //   registers. Activations are recomputed, never stored.
 #include <type_traits>
 
@@ -23,58 +25,149 @@
 
 namespace nasg {
 
-template <int H, int K, int PREC>
-struct LargeNet {
-  typedef Mlp<H, K, PREC> M;
-  typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
+// ------------------------------------------------------------------ BF16 ----
+// Stage order of one tile's forward: layer 0, hidden layers 1..NH-1, output
+// rows [0, 4K) and [4K, 8K); stage s computes from buffer s % 2 while stage
+// s + 1 is copied into the other. With NH even the stage after the forward
+// (the caller's choice) lands in buffer 0 again.
+template <int H, int K>
+struct NetBf16 {
+  typedef Mlp<H, K, 1> M;
+  typedef __bf16 W;
+  static constexpr int NH = 4;
+  static constexpr int MTH = H / 16, MTO = K / 2, KQ = K / 4, HALF_O = MTO / 2;
+  static constexpr int KBO = K / 4;                        // 32-wide blocks over the 8K output rows
+  static constexpr int BUF = (H * H > 4 * K * H) ? H * H : 4 * K * H;   // elements per buffer
+  static constexpr int OB_HALF = (H / 32) * KBO * 512;    // half of the output layer's backward fragments
+  static constexpr int SP = kWGV + 8;                      // staging pitch (bf16)
+  static constexpr int RMAX = 8 * K;
+  static_assert(NH % 2 == 0, "buffer parity assumes an even number of hidden layers");
+  static_assert(H * H <= BUF && 4 * K * H <= BUF && OB_HALF <= BUF, "stage exceeds a buffer");
+
+  __device__ static Bf16Layout layout() { return Bf16Layout{NetDims{H, NH, K}}; }
+  __device__ static void dma(W* dst, const W* src, int elems) { lds_dma(dst, src, elems * 2); }
+  __device__ static void sync_stage() {
+    lds_dma_wait();
+    __syncthreads();
+  }
+  // Layer 0 into b0, awaited: the first tile of a workgroup.
+  __device__ static void begin(const W* wg, W* b0) {
+    dma(b0, wg + layout().fwd_off(0), H * 16);
+    sync_stage();
+  }
+
+  // Forward of one tile with layer 0 resident in b0; leaves `next` (elems)
+  // in b0 when it returns.
+  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&h)[NH][MTH][4],
+                                 float (&out)[MTO][4], const W* next, int next_elems, int lane) {
+    const Bf16Layout Lt = layout();
+    dma(b1, wg + Lt.fwd_off(1), H * H);
+    M::layer0(b0, x, h[0], lane);
+    sync_stage();
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      W* cur = (l & 1) ? b1 : b0;
+      W* oth = (l & 1) ? b0 : b1;
+      if (l + 1 < NH) dma(oth, wg + Lt.fwd_off(l + 1), H * H);
+      else dma(oth, wg + Lt.fwd_off(NH), HALF_O * 16 * H);
+      float y[MTH][4];
+      M::template gemm<MTH>(cur, h[l - 1], y, lane);
+#pragma unroll
+      for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[l][mt][i] = relu(y[mt][i]);
+      sync_stage();
+    }
+    // output rows, half 0 in b0 and half 1 in b1
+    dma(b1, wg + Lt.fwd_off(NH) + HALF_O * 16 * H, HALF_O * 16 * H);
+    {
+      float part[HALF_O][4];
+      M::template gemm<HALF_O>(b0, h[NH - 1], part, lane);
+#pragma unroll
+      for (int mt = 0; mt < HALF_O; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[mt][i] = part[mt][i];
+    }
+    sync_stage();
+    dma(b0, next, next_elems);
+    {
+      float part[HALF_O][4];
+      M::template gemm<HALF_O>(b1, h[NH - 1], part, lane);
+#pragma unroll
+      for (int mt = 0; mt < HALF_O; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[HALF_O + mt][i] = part[mt][i];
+    }
+    sync_stage();
+  }
+
+  // Forward that leaves the next tile's layer 0 in b0 (query, gradient).
+  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&h)[NH][MTH][4],
+                                 float (&out)[MTO][4], int lane) {
+    forward(wg, b0, b1, x, h, out, wg + layout().fwd_off(0), H * 16, lane);
+  }
+};
+
+// dp[MT0 .. MT0+NMT) of W^T dl from backward fragments [NMT][KB][64] at buf;
+// b holds dl as B operands.
+template <int KB, int NMT, int MT0, int MTP>
+__device__ __forceinline__ void dgrad_rows(const __bf16* buf, const bf16x8 (&b)[KB], float (&dp)[MTP][4],
+                                           int lane) {
+  const bf16x8* frag = reinterpret_cast<const bf16x8*>(buf);
+#pragma unroll
+  for (int mt = 0; mt < NMT; ++mt) {
+    f32x4 acc = zero4();
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[i];
+  }
+}
+
+// ------------------------------------------------------------------ FP32 ----
+template <int H, int K>
+struct NetF32 {
+  typedef Mlp<H, K, 0> M;
+  typedef float W;
   static constexpr int NH = 4;
   static constexpr int MTH = H / 16, MTO = K / 2, KQ = K / 4;
-  static constexpr int CH = 64;              // FP32 rows per LDS chunk
-  static constexpr int TPC = CH / 16;        // FP32 row tiles per chunk
-  static constexpr int PH = H + 1;           // FP32 pitch of hidden and output layers
-  static constexpr int P0 = kInPadded + 1;   // FP32 pitch of layer 0
-  static constexpr int BUF_ELEMS = PREC == 1 ? ((8 * K * H > H * H) ? 8 * K * H : H * H)
-                                             : ((CH * PH > H * P0) ? CH * PH : H * P0);
-  static constexpr int SP = PREC == 1 ? kWGV + 8 : kWGV + 4;   // staging pitch
+  static constexpr int CH = 64;              // rows per LDS chunk
+  static constexpr int TPC = CH / 16;        // row tiles per chunk
+  static constexpr int PH = H + 1;           // pitch of hidden and output layers
+  static constexpr int P0 = kInPadded + 1;   // pitch of layer 0
+  static constexpr int BUF = (CH * PH > H * P0) ? CH * PH : H * P0;
+  static constexpr int SP = kWGV + 4;
   static constexpr int RMAX = 8 * K;
 
+  __device__ static F32Layout layout() { return F32Layout{NetDims{H, NH, K}}; }
   // Replace the LDS weight buffer's contents (whole workgroup).
   __device__ static void wstage(W* buf, const W* src, int elems) {
     __syncthreads();
-    block_copy_to_lds(buf, src, elems * (int)sizeof(W));
+    lds_dma(buf, src, elems * (int)sizeof(W));
+    lds_dma_wait();
     __syncthreads();
   }
 
-  // y = W_l h over all MT_*16 rows of layer l, streaming the weights
+  // y = W_l h over all MT_*16 rows of layer l, 64 rows at a time
   template <int MT_>
   __device__ static void layer(const W* wg, W* buf, int l, const float (&in)[MTH][4], float (&y)[MT_][4],
                                int lane) {
-    if constexpr (PREC == 1) {
-      const Bf16Layout Lt{NetDims{H, NH, K}};
-      wstage(buf, wg + Lt.fwd_off(l), MT_ * 16 * H);
-      M::template gemm<MT_>(buf, in, y, lane);
-    } else {
-      const F32Layout Lt{NetDims{H, NH, K}};
+    const F32Layout Lt = layout();
 #pragma unroll
-      for (int ch = 0; ch < MT_ / TPC; ++ch) {
-        wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
-        float part[TPC][4];
-        M::template gemm<TPC>(buf, in, part, lane);   // rows ch*CH .. ch*CH + CH - 1
+    for (int ch = 0; ch < MT_ / TPC; ++ch) {
+      wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
+      float part[TPC][4];
+      M::template gemm<TPC>(buf, in, part, lane);   // rows ch*CH .. ch*CH + CH - 1
 #pragma unroll
-        for (int t = 0; t < TPC; ++t)
+      for (int t = 0; t < TPC; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) y[ch * TPC + t][i] = part[t][i];
-      }
+        for (int i = 0; i < 4; ++i) y[ch * TPC + t][i] = part[t][i];
     }
   }
 
-  __device__ static void forward(const W* wg, W* buf, const typename M::Input& x, float (&h)[NH][MTH][4],
+  __device__ static void forward(const W* wg, W* buf, W*, const typename M::Input& x, float (&h)[NH][MTH][4],
                                  float (&out)[MTO][4], int lane) {
-    if constexpr (PREC == 1) {
-      wstage(buf, wg + Bf16Layout{NetDims{H, NH, K}}.fwd_off(0), H * 16);
-    } else {
-      wstage(buf, wg + F32Layout{NetDims{H, NH, K}}.off(0), H * P0);
-    }
+    wstage(buf, wg + layout().off(0), H * P0);
     M::layer0(buf, x, h[0], lane);
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
@@ -88,41 +181,38 @@ struct LargeNet {
     layer<MTO>(wg, buf, NH, h[NH - 1], out, lane);
   }
 
-  // dp = W_l^T dl (rows of layer l = RT*16), streaming the backward weights
+  // dp = W_l^T dl (rows of layer l = RT*16), 64 rows of weights at a time
   template <int RT>
   __device__ static void dgrad_layer(const W* wg, W* buf, int l, const float (&dl)[RT][4], float (&dp)[MTH][4],
                                      int lane) {
-    if constexpr (PREC == 1) {
-      const Bf16Layout Lt{NetDims{H, NH, K}};
-      wstage(buf, wg + Lt.bwd_off(l), RT * 16 * H);
-      dgrad<H, K, 1, RT>(buf, dl, dp, lane);
-    } else {
-      const F32Layout Lt{NetDims{H, NH, K}};
-      const int g = lane >> 4, c = lane & 15;
-      f32x4 acc[MTH];
+    const F32Layout Lt = layout();
+    const int g = lane >> 4, c = lane & 15;
+    f32x4 acc[MTH];
 #pragma unroll
-      for (int mt = 0; mt < MTH; ++mt) acc[mt] = zero4();
-      // slot (kb, g) of the contraction is row (kb/4)*16 + 4g + kb%4 of layer l,
-      // held in dl[kb/4][kb%4]; chunk ch holds rows [CH*ch, CH*ch + CH)
+    for (int mt = 0; mt < MTH; ++mt) acc[mt] = zero4();
+    // slot (kb, g) of the contraction is row (kb/4)*16 + 4g + kb%4 of layer l,
+    // held in dl[kb/4][kb%4]; chunk ch holds rows [CH*ch, CH*ch + CH)
 #pragma unroll
-      for (int ch = 0; ch < RT / TPC; ++ch) {
-        wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
-#pragma unroll
-        for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-          for (int kk = 0; kk < 4 * TPC; ++kk) {
-            const int kb = 4 * TPC * ch + kk;
-            const int r = ((kb >> 2) - TPC * ch) * 16 + 4 * g + (kb & 3);
-            acc[mt] = mfma_f32_4(buf[r * PH + mt * 16 + c], dl[kb >> 2][kb & 3], acc[mt]);
-          }
-      }
+    for (int ch = 0; ch < RT / TPC; ++ch) {
+      wstage(buf, wg + Lt.off(l) + (int64_t)ch * CH * PH, CH * PH);
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dp[mt][i] = acc[mt][i];
+        for (int kk = 0; kk < 4 * TPC; ++kk) {
+          const int kb = 4 * TPC * ch + kk;
+          const int r = ((kb >> 2) - TPC * ch) * 16 + 4 * g + (kb & 3);
+          acc[mt] = mfma_f32_4(buf[r * PH + mt * 16 + c], dl[kb >> 2][kb & 3], acc[mt]);
+        }
     }
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[mt][i];
   }
 };
+
+template <int H, int K, int PREC>
+using LargeNet = typename std::conditional<PREC == 1, NetBf16<H, K>, NetF32<H, K>>::type;
 
 // Hidden activations kept by the backward kernels: BF16 pairs for the BF16
 // network (used only as BF16 staging operands and as ReLU masks h > 0),
@@ -179,6 +269,24 @@ __device__ __forceinline__ void stage_act(S* st, const Act<PREC, MTH>& h, int wa
   stage_rows<S, MTH, SP>(st, x, wave, lane);
 }
 
+// Layer 0's input (features, the constant one, zero padding) of the tile's
+// 64 vertices as staging columns k = 0..15.
+template <typename S, int SP>
+__device__ __forceinline__ void stage_input(S* st, const float* feat, int64_t ld, int64_t v, bool valid, int wave,
+                                            int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 4 * g + j;
+    float xv = 0.0f;
+    if (valid) {
+      if (k < kInFeatures) xv = feat[(int64_t)k * ld + v];
+      else if (k == kInFeatures) xv = 1.0f;
+    }
+    st[k * SP + wave * 16 + c] = (S)xv;
+  }
+}
+
 // dL/d(raw outputs) of 16 vertices: BF16 as the output layer's dgrad B
 // operands (K/4 16-byte slots per lane); FP32 as the accumulator image
 // (K/2 16-byte slots per lane).
@@ -219,6 +327,12 @@ struct DOut {
       }
     }
   }
+  // BF16 only: the stored slots are exactly the output layer's dgrad B operands
+  __device__ static void load_operands(const void* base, int64_t tile16, bf16x8 (&b)[KBO], int lane) {
+    const bf16x8* s = reinterpret_cast<const bf16x8*>(base) + tile16 * KBO * 64 + lane;
+#pragma unroll
+    for (int kb = 0; kb < KBO; ++kb) b[kb] = s[kb * 64];
+  }
 };
 
 // ---------------------------------------------------------------- query ----
@@ -229,11 +343,13 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
   typedef typename N::W W;
   constexpr int KQ = N::KQ;
   extern __shared__ __align__(16) unsigned char smem[];
-  W* buf = reinterpret_cast<W*>(smem);
+  W* b0 = reinterpret_cast<W*>(smem);
+  W* b1 = b0 + N::BUF;
   const W* wg = reinterpret_cast<const W*>(a.wpack);
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
+  if constexpr (PREC == 1) N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * kWGV + wave * 16 + c;
@@ -241,7 +357,7 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
     float h[N::NH][N::MTH][4];
     float out[N::MTO][4];
-    N::forward(wg, buf, x, h, out, lane);
+    N::forward(wg, b0, b1, x, h, out, lane);
     if (MODE == 1) {
       if (valid) {
 #pragma unroll
@@ -290,25 +406,29 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
   typedef typename N::W W;
   constexpr int KQ = N::KQ, MTO = N::MTO;
   extern __shared__ __align__(16) unsigned char smem[];
-  W* buf = reinterpret_cast<W*>(smem);
+  W* b0 = reinterpret_cast<W*>(smem);
+  W* b1 = b0 + N::BUF;
   const W* wg = reinterpret_cast<const W*>(a.wpack);
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
   const float inv_b = 1.0f / (float)a.B;
   double loss_sum = 0.0, w_sum = 0.0;
+  if constexpr (PREC == 1) N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    float h[N::NH][N::MTH][4];
-    float out[MTO][4];
-    N::forward(wg, buf, x, h, out, lane);
     float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f;
     if (valid) {
       vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
       wj = a.w[v];
+    }
+    float h[N::NH][N::MTH][4];
+    float out[MTO][4];
+    N::forward(wg, b0, b1, x, h, out, lane);
+    {
       const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
     }
@@ -335,24 +455,29 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
   }
 }
 
-// ------------------------------------------------------------- backward ----
+// ------------------------------------------------------- backward, BF16 ----
 // GROUP 0: weight gradients of the output layer and the last hidden layer;
-// GROUP 1: of hidden layers NH-2 .. 1 and layer 0.
-template <int H, int K, int PREC, int GROUP>
+// GROUP 1: of hidden layers NH-2 .. 1 and layer 0. Each continues the
+// forward's weight pipeline through its dgrad stages and ends a tile with
+// the next tile's layer 0 resident.
+template <int H, int K, int GROUP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void bwd_kernel(LargeTrainArgs a) {
-  typedef LargeNet<H, K, PREC> N;
+void bwd_bf16_kernel(LargeTrainArgs a) {
+  typedef NetBf16<H, K> N;
   typedef typename N::M M;
-  typedef typename N::W W;
-  typedef typename std::conditional<PREC == 1, __bf16, float>::type S;
-  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, SP = N::SP;
-  constexpr int RTW_H = (MTH + 3) / 4, RTW_O = (MTO + 3) / 4, CTH = H / 16;
+  typedef __bf16 W;
+  typedef __bf16 S;
+  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, SP = N::SP, KBO = N::KBO;
+  constexpr int RTW_H = (MTH + 3) / 4, RTW_O = (MTO + 3) / 4, CTH = H / 16, HALF_H = MTH / 2;
   extern __shared__ __align__(16) unsigned char smem[];
-  W* buf = reinterpret_cast<W*>(smem);
-  S* dst = reinterpret_cast<S*>(smem + N::BUF_ELEMS * sizeof(W));
+  W* bufA = reinterpret_cast<W*>(smem);
+  W* bufB = bufA + N::BUF;
+  S* dst = reinterpret_cast<S*>(smem + 2 * N::BUF * sizeof(W));
   S* hst = dst + N::RMAX * SP;
   const W* wg = reinterpret_cast<const W*>(a.wpack);
+  const Bf16Layout Lt = N::layout();
   const NetDims dims{H, NH, K};
+  const W* out_bwd = wg + Lt.bwd_off(NH);   // [H/16][KBO][64][8]: halves over the first index
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
@@ -385,48 +510,187 @@ void bwd_kernel(LargeTrainArgs a) {
 #pragma unroll
     for (int ct = 0; ct < CTH; ++ct) accO[r][ct] = zero4();
 
+  W* b0 = bufA;
+  W* b1 = bufB;
+  N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    Act<PREC, MTH> hp[NH];
+    Act<1, MTH> hp[NH];
     {
       float h[NH][MTH][4];
       float out[MTO][4];
-      N::forward(wg, buf, x, h, out, lane);
+      N::forward(wg, b0, b1, x, h, out, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
+#pragma unroll
+      for (int l = 0; l < NH; ++l) hp[l].set(h[l]);
+    }
+    bf16x8 bo[KBO];
+    DOut<K, 1>::load_operands(a.dout, tile * 4 + wave, bo, lane);
+    float dh[MTH][4];
+    if constexpr (GROUP == 0) {
+      float dl[MTO][4];
+      DOut<K, 1>::load(a.dout, tile * 4 + wave, dl, lane);
+      stage_rows<S, MTO, SP>(dst, dl, wave, lane);
+      stage_act<S, 1, MTH, SP>(hst, hp[NH - 1], wave, lane);
+      N::dma(b1, out_bwd + N::OB_HALF, N::OB_HALF);
+      dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
+      N::sync_stage();                                  // also publishes the staging
+      wgrad_tiles<1, S, SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
+      N::dma(b0, wg + Lt.fwd_off(0), H * 16);           // the next tile's layer 0
+      dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
+      mask_relu<1, MTH>(dh, hp[NH - 1]);
+      N::sync_stage();                                  // the staging has been read
+      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
+      stage_act<S, 1, MTH, SP>(hst, hp[NH - 2], wave, lane);
+      __syncthreads();
+      wgrad_tiles<1, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
+      // the next writes to the staging area follow the next tile's forward,
+      // whose barriers order them after these reads
+    } else {
+      N::dma(b1, out_bwd + N::OB_HALF, N::OB_HALF);
+      dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
+      N::sync_stage();
+      N::dma(b0, wg + Lt.bwd_off(NH - 1), H * H);
+      dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
+      mask_relu<1, MTH>(dh, hp[NH - 1]);
+      N::sync_stage();
+      float d2[MTH][4];
+      N::dma(b1, wg + Lt.bwd_off(NH - 2), H * H);
+      dgrad<H, K, 1, MTH>(b0, dh, d2, lane);             // through hidden layer NH-1
+      mask_relu<1, MTH>(d2, hp[NH - 2]);
+      N::sync_stage();
+      W* cur = b1;   // holds hidden layer l's backward fragments
+      W* oth = b0;
+#pragma unroll
+      for (int l = NH - 2; l >= 1; --l) {
+        stage_rows<S, MTH, SP>(dst, d2, wave, lane);
+        stage_act<S, 1, MTH, SP>(hst, hp[l - 1], wave, lane);
+        if (l > 1) N::dma(oth, wg + Lt.bwd_off(l - 1), H * H);
+        else N::dma(oth, wg + Lt.fwd_off(0), H * 16);   // the next tile's layer 0
+        float dn[MTH][4];
+        dgrad<H, K, 1, MTH>(cur, d2, dn, lane);
+        mask_relu<1, MTH>(dn, hp[l - 1]);
+        N::sync_stage();                                // also publishes the staging
+        wgrad_tiles<1, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) d2[mt][i] = dn[mt][i];
+        W* t = cur; cur = oth; oth = t;
+      }
+      stage_rows<S, MTH, SP>(dst, d2, wave, lane);
+      stage_input<S, SP>(hst, a.feat, a.ld, v, valid, wave, lane);
+      __syncthreads();
+      wgrad_tiles<1, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      b0 = cur;   // the next tile's layer 0
+      b1 = oth;
+    }
+  }
+
+  float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
+  if constexpr (GROUP == 0) {
+    flush_tiles<RTW_O, CTH>(part, dims, NH, rt_o, nrt_o, accO, lane);
+    flush_tiles<RTW_H, CTH>(part, dims, NH - 1, rt_h, nrt_h, accT, lane);
+  } else {
+#pragma unroll
+    for (int l = 1; l <= NH - 2; ++l) flush_tiles<RTW_H, CTH>(part, dims, l, rt_h, nrt_h, accM[l - 1], lane);
+    flush_tiles<RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
+  }
+}
+
+// ------------------------------------------------------- backward, FP32 ----
+template <int H, int K, int GROUP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void bwd_f32_kernel(LargeTrainArgs a) {
+  typedef NetF32<H, K> N;
+  typedef typename N::M M;
+  typedef float W;
+  typedef float S;
+  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, SP = N::SP;
+  constexpr int RTW_H = (MTH + 3) / 4, RTW_O = (MTO + 3) / 4, CTH = H / 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  W* buf = reinterpret_cast<W*>(smem);
+  S* dst = reinterpret_cast<S*>(smem + N::BUF * sizeof(W));
+  S* hst = dst + N::RMAX * SP;
+  const W* wg = reinterpret_cast<const W*>(a.wpack);
+  const NetDims dims{H, NH, K};
+  const int lane = lane_id();
+  const int g = lane >> 4, c = lane & 15;
+  const int wave = threadIdx.x >> 6;
+
+  int rt_h[RTW_H], rt_o[RTW_O];
+  int nrt_h = 0, nrt_o = 0;
+#pragma unroll
+  for (int r = 0; r < RTW_H; ++r) { rt_h[r] = wave + 4 * r; if (rt_h[r] < MTH) nrt_h = r + 1; }
+#pragma unroll
+  for (int r = 0; r < RTW_O; ++r) { rt_o[r] = wave + 4 * r; if (rt_o[r] < MTO) nrt_o = r + 1; }
+
+  constexpr int NO = GROUP == 0 ? RTW_O : 1;
+  constexpr int NM = GROUP == 1 ? NH - 2 : 1;
+  f32x4 accO[NO][CTH];
+  f32x4 accT[RTW_H][CTH];
+  f32x4 accM[NM][RTW_H][CTH];
+  f32x4 acc0[RTW_H][1];
+#pragma unroll
+  for (int r = 0; r < RTW_H; ++r) {
+    acc0[r][0] = zero4();
+#pragma unroll
+    for (int ct = 0; ct < CTH; ++ct) {
+      accT[r][ct] = zero4();
+#pragma unroll
+      for (int l = 0; l < NM; ++l) accM[l][r][ct] = zero4();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NO; ++r)
+#pragma unroll
+    for (int ct = 0; ct < CTH; ++ct) accO[r][ct] = zero4();
+
+  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t v = tile * kWGV + wave * 16 + c;
+    const bool valid = v < a.B;
+    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    Act<0, MTH> hp[NH];
+    {
+      float h[NH][MTH][4];
+      float out[MTO][4];
+      N::forward(wg, buf, nullptr, x, h, out, lane);
 #pragma unroll
       for (int l = 0; l < NH; ++l) hp[l].set(h[l]);
     }
     float dl[MTO][4];
-    DOut<K, PREC>::load(a.dout, tile * 4 + wave, dl, lane);
+    DOut<K, 0>::load(a.dout, tile * 4 + wave, dl, lane);
     float dh[MTH][4];
     if constexpr (GROUP == 0) {
       stage_rows<S, MTO, SP>(dst, dl, wave, lane);
-      stage_act<S, PREC, MTH, SP>(hst, hp[NH - 1], wave, lane);
+      stage_act<S, 0, MTH, SP>(hst, hp[NH - 1], wave, lane);
       N::template dgrad_layer<MTO>(wg, buf, NH, dl, dh, lane);   // its weight staging publishes the above
-      mask_relu<PREC, MTH>(dh, hp[NH - 1]);
-      wgrad_tiles<PREC, S, SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
+      mask_relu<0, MTH>(dh, hp[NH - 1]);
+      wgrad_tiles<0, S, SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
       __syncthreads();
       stage_rows<S, MTH, SP>(dst, dh, wave, lane);
-      stage_act<S, PREC, MTH, SP>(hst, hp[NH - 2], wave, lane);
+      stage_act<S, 0, MTH, SP>(hst, hp[NH - 2], wave, lane);
       __syncthreads();
-      wgrad_tiles<PREC, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
+      wgrad_tiles<0, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
       __syncthreads();
     } else {
       N::template dgrad_layer<MTO>(wg, buf, NH, dl, dh, lane);
-      mask_relu<PREC, MTH>(dh, hp[NH - 1]);
+      mask_relu<0, MTH>(dh, hp[NH - 1]);
       float d2[MTH][4];
       N::template dgrad_layer<MTH>(wg, buf, NH - 1, dh, d2, lane);
-      mask_relu<PREC, MTH>(d2, hp[NH - 2]);
+      mask_relu<0, MTH>(d2, hp[NH - 2]);
 #pragma unroll
       for (int l = NH - 2; l >= 1; --l) {
         stage_rows<S, MTH, SP>(dst, d2, wave, lane);
-        stage_act<S, PREC, MTH, SP>(hst, hp[l - 1], wave, lane);
+        stage_act<S, 0, MTH, SP>(hst, hp[l - 1], wave, lane);
         float dn[MTH][4];
         N::template dgrad_layer<MTH>(wg, buf, l, d2, dn, lane);   // publishes the staging
-        mask_relu<PREC, MTH>(dn, hp[l - 1]);
-        wgrad_tiles<PREC, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
+        mask_relu<0, MTH>(dn, hp[l - 1]);
+        wgrad_tiles<0, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
         __syncthreads();
 #pragma unroll
         for (int mt = 0; mt < MTH; ++mt)
@@ -434,18 +698,9 @@ void bwd_kernel(LargeTrainArgs a) {
           for (int i = 0; i < 4; ++i) d2[mt][i] = dn[mt][i];
       }
       stage_rows<S, MTH, SP>(dst, d2, wave, lane);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
-        float xv = 0.0f;
-        if (valid) {
-          if (k < kInFeatures) xv = a.feat[(int64_t)k * a.ld + v];
-          else if (k == kInFeatures) xv = 1.0f;
-        }
-        hst[k * SP + wave * 16 + c] = (S)xv;
-      }
+      stage_input<S, SP>(hst, a.feat, a.ld, v, valid, wave, lane);
       __syncthreads();
-      wgrad_tiles<PREC, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      wgrad_tiles<0, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
       __syncthreads();
     }
   }
@@ -467,10 +722,18 @@ static hipError_t set_lds(Kern kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// LDS of the weight buffers, and of the backward kernels (weights + staging)
+template <int H, int K, int PREC>
+struct LargeLds {
+  typedef LargeNet<H, K, PREC> N;
+  static constexpr size_t fwd = (size_t)(PREC == 1 ? 2 : 1) * N::BUF * sizeof(typename N::W);
+  static constexpr size_t bwd = fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
+  static_assert(bwd <= 160 * 1024, "LDS budget");
+};
+
 template <int H, int K, int PREC>
 static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t st) {
-  typedef LargeNet<H, K, PREC> N;
-  const size_t shmem = (size_t)N::BUF_ELEMS * sizeof(typename N::W);
+  const size_t shmem = LargeLds<H, K, PREC>::fwd;
   auto kern = mode == 0 ? large_query_kernel<H, K, PREC, 0> : large_query_kernel<H, K, PREC, 1>;
   static bool attr[2] = {false, false};
   if (!attr[mode]) {
@@ -485,15 +748,19 @@ static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t
   return hipGetLastError();
 }
 
+int gradout_workgroups(int64_t B, int num_cus) {
+  const int64_t t = (B + kWGV - 1) / kWGV;
+  const int64_t cap = 2LL * (num_cus < kMaxTrainWG ? num_cus : kMaxTrainWG);
+  return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
+}
+
 template <int H, int K, int PREC>
-static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, hipStream_t st) {
-  typedef LargeNet<H, K, PREC> N;
-  typedef typename std::conditional<PREC == 1, __bf16, float>::type S;
-  const size_t sh_fwd = (size_t)N::BUF_ELEMS * sizeof(typename N::W);
-  const size_t sh_bwd = sh_fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(S);
+static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_grad, hipStream_t st) {
+  const size_t sh_fwd = LargeLds<H, K, PREC>::fwd;
+  const size_t sh_bwd = LargeLds<H, K, PREC>::bwd;
   auto k_grad = gradout_kernel<H, K, PREC>;
-  auto k_bwd0 = bwd_kernel<H, K, PREC, 0>;
-  auto k_bwd1 = bwd_kernel<H, K, PREC, 1>;
+  auto k_bwd0 = PREC == 1 ? bwd_bf16_kernel<H, K, 0> : bwd_f32_kernel<H, K, 0>;
+  auto k_bwd1 = PREC == 1 ? bwd_bf16_kernel<H, K, 1> : bwd_f32_kernel<H, K, 1>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = set_lds(k_grad, sh_fwd);
@@ -502,7 +769,7 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, hipStr
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_grad, dim3(n_wg), dim3(256), sh_fwd, st, a);
+  hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), sh_fwd, st, a);
   hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(256), sh_bwd, st, a);
   hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(256), sh_bwd, st, a);
   return hipGetLastError();
@@ -516,9 +783,10 @@ hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mo
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st) {
+hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, int n_grad,
+                              hipStream_t st) {
 #define NASG_CASE(h, k, p) \
-  if (H == h && K == k && prec == p) return launch_large_train_t<h, k, p>(a, n_wg, st);
+  if (H == h && K == k && prec == p) return launch_large_train_t<h, k, p>(a, n_wg, n_grad, st);
   NASG_FOR_EACH_LARGE_NET(NASG_CASE)
 #undef NASG_CASE
   return hipErrorInvalidValue;

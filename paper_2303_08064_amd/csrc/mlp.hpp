@@ -57,6 +57,52 @@ struct Mlp<H, K, 1> {
     }
   }
 
+  // Next layer's B operands from a layer's pre-activation accumulators, the
+  // ReLU applied to the packed BF16 values (one 16-bit integer max per pair:
+  // BF16 keeps the sign bit on top, and rounding never changes a sign, so
+  // this equals rounding relu(y)).
+  __device__ static uint32_t relu_pair(float lo, float hi) {
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) short s16x2;
+    const bf16x2 p = __builtin_convertvector((f32x2){lo, hi}, bf16x2);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2)0));
+  }
+  __device__ static void relu_operands(const float (&y)[MTH][4], bf16x8 (&b)[KBH]) {
+    typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+#pragma unroll
+    for (int kb = 0; kb < KBH; ++kb) {
+      const u32x4 w = {relu_pair(y[2 * kb][0], y[2 * kb][1]), relu_pair(y[2 * kb][2], y[2 * kb][3]),
+                       relu_pair(y[2 * kb + 1][0], y[2 * kb + 1][1]), relu_pair(y[2 * kb + 1][2], y[2 * kb + 1][3])};
+      b[kb] = __builtin_bit_cast(bf16x8, w);
+    }
+  }
+
+  // W_0 x without the ReLU
+  __device__ static void layer0_linear(const __bf16* lds, Input x, float (&y)[MTH][4], int lane) {
+    const bf16x4* frag = reinterpret_cast<const bf16x4*>(lds);
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt) {
+      f32x4 acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
+    }
+  }
+
+  // out = W in over MT row tiles from ready B operands
+  template <int MT>
+  __device__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KBH; ++kb) acc = mfma_bf16_32(frag[(mt * KBH + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[mt][i] = acc[i];
+    }
+  }
+
   // out = W in over MT row tiles, W fragments [MT][KBH][64] at `lds`
   template <int MT>
   __device__ static void gemm(const __bf16* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
@@ -177,6 +223,30 @@ struct Forward {
       }
     }
     M::template gemm<M::MTO>(layer_ptr(lds, nh, nh), last, out, lane);
+  }
+
+  // Forward for queries (no activations kept): in BF16 the layers pass
+  // packed, ReLU'd B operands; the same values as run().
+  __device__ static void run_query(const W* lds, int nh, const typename M::Input& x, float (&out)[M::MTO][4],
+                                   int lane) {
+    if constexpr (PREC == 1) {
+      float y[M::MTH][4];
+      bf16x8 b[M::KBH];
+      M::layer0_linear(layer_ptr(lds, 0, nh), x, y, lane);
+      M::relu_operands(y, b);
+#pragma unroll
+      for (int l = 1; l < NHMAX; ++l) {
+        if (l < nh) {
+          M::template gemm_op<M::MTH>(layer_ptr(lds, l, nh), b, y, lane);
+          M::relu_operands(y, b);
+        }
+      }
+      M::template gemm_op<M::MTO>(layer_ptr(lds, nh, nh), b, out, lane);
+    } else {
+      float h[NHMAX][M::MTH][4];
+      float last[M::MTH][4];
+      run(lds, nh, x, h, last, out, lane);
+    }
   }
 };
 

@@ -40,17 +40,20 @@ __device__ __forceinline__ float expm1f_(float x) {
   return fsel(fabsf(x) < 0.125f, p, e);
 }
 
-// log(1 + y) for y > -1, accurate in relative terms: series to y^6 for
-// |y| < 1/16 (truncation below 1e-8 relative), log(1 + y) elsewhere.
-__device__ __forceinline__ float log1pf_(float y) {
+// log(1 + y) by its series to y^6 (truncation below 1e-8 relative for |y| < 1/16).
+__device__ __forceinline__ float log1p_series(float y) {
   float p = fmaf(y, -1.0f / 6.0f, 1.0f / 5.0f);
   p = fmaf(y, p, -1.0f / 4.0f);
   p = fmaf(y, p, 1.0f / 3.0f);
   p = fmaf(y, p, -0.5f);
   p = fmaf(y, p, 1.0f);
-  p = p * y;
-  float l = flog(1.0f + y);
-  return fsel(fabsf(y) < 0.0625f, p, l);
+  return p * y;
+}
+
+// log(1 + y) for y > -1, accurate in relative terms: the series for
+// |y| < 1/16, log(1 + y) elsewhere.
+__device__ __forceinline__ float log1pf_(float y) {
+  return fsel(fabsf(y) < 0.0625f, log1p_series(y), flog(1.0f + y));
 }
 
 // tanh(o/2) = 2 sigmoid(o) - 1 (Tab. "decoding") as m/(2 - m) with m = 1 - e^{-|o|},
@@ -195,8 +198,9 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   float sx = vx + L.zx, sy = vy + L.zy, sz = vz + L.zz;
   float w = 0.25f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));   // 1 - u
   float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));   // u
-  // log u: series of log(1 - w) near the axis, else log of the better-conditioned one
-  float lw = log1pf_(-w);
+  // log u: series of log(1 - w) near the axis, else the log of the
+  // better-conditioned of 1 - w and u (one log either way)
+  float lw = log1p_series(-w);
   float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
   r.L = fsel(w < 0.0625f, lw, lu);
   r.u = u;

@@ -14,7 +14,7 @@
 namespace nasg {
 
 template <int H, int K, int PREC, int MODE>   // MODE 0: query, 1: raw forward only
-__global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 3 : 1))) void query_kernel(QueryArgs a) {
   constexpr int NHMAX = 4;
   constexpr int KQ = K / 4;
   typedef Mlp<H, K, PREC> M;
@@ -34,10 +34,8 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     const int64_t v = tile * kTileV + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    float h[NHMAX][M::MTH][4];
-    float last[M::MTH][4];
     float out[M::MTO][4];
-    F::run(wts, a.nh, x, h, last, out, lane);
+    F::run_query(wts, a.nh, x, out, lane);
 
     if (MODE == 1) {
       // raw outputs in canonical row order: accumulator t of lane group g is

@@ -18,7 +18,6 @@
 
 namespace nasg {
 
-constexpr int kMaxTrainWG = 256;
 
 template <int H, int K, int PREC>
 struct TrainCfg {
@@ -288,7 +287,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   if (threadIdx.x == 0) a.norm_partial[blockIdx.x] = red[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double ls = 0.0, ws = 0.0;
-    for (int wg = 0; wg < a.n_wg; ++wg) { ls += a.loss_partial[2 * wg]; ws += a.loss_partial[2 * wg + 1]; }
+    for (int wg = 0; wg < a.n_loss; ++wg) { ls += a.loss_partial[2 * wg]; ws += a.loss_partial[2 * wg + 1]; }
     a.stats[0] = ls / (double)a.B;
     a.stats[1] = ws;
     a.stats[3] = ls;
