@@ -67,14 +67,14 @@ __device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int 
     for (int i = 0; i < 4; ++i) buf[(mt * 16 + 4 * g + i) * SP + wave * 16 + c] = (S)x[mt][i];
 }
 
-// acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the 64 staged vertices
-template <int PREC, typename S, int SP, int NR, int NC>
+// acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the NV staged vertices
+template <int PREC, typename S, int SP, int NR, int NC, int NV = kWGV>
 __device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const int (&rt)[NR], int nrt,
                                             f32x4 (&acc)[NR][NC], int lane) {
   const int g = lane >> 4, c = lane & 15;
   if constexpr (PREC == 1) {
 #pragma unroll
-    for (int vb = 0; vb < kWGV / 32; ++vb) {
+    for (int vb = 0; vb < NV / 32; ++vb) {
       bf16x8 hb[NC];
 #pragma unroll
       for (int ct = 0; ct < NC; ++ct)
@@ -90,7 +90,7 @@ __device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const in
     }
   } else {
 #pragma unroll
-    for (int vb = 0; vb < kWGV / 4; ++vb) {
+    for (int vb = 0; vb < NV / 4; ++vb) {
       float hb[NC];
 #pragma unroll
       for (int ct = 0; ct < NC; ++ct) hb[ct] = hst[(ct * 16 + c) * SP + vb * 4 + g];

@@ -26,6 +26,60 @@
 namespace nasg {
 
 // ------------------------------------------------------------------ BF16 ----
+// RT*16 rows of one 16-vertex block in the accumulator layout as BF16 pairs:
+// p[mt][k] holds rows mt*16 + 4g + 2k (low half) and + 1 (high half) of
+// vertex c at lane (g, c). Four consecutive words are exactly one 32-wide
+// MFMA B operand, so hidden activations, deltas and the raw-output gradient
+// move between layers, masks and LDS staging without conversions.
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+template <int RT>
+struct Pk {
+  uint32_t p[RT][2];
+  __device__ void from_ops(const bf16x8 (&b)[RT / 2]) {
+#pragma unroll
+    for (int kb = 0; kb < RT / 2; ++kb) {
+      const u32x4 w = __builtin_bit_cast(u32x4, b[kb]);
+      p[2 * kb][0] = w[0]; p[2 * kb][1] = w[1]; p[2 * kb + 1][0] = w[2]; p[2 * kb + 1][1] = w[3];
+    }
+  }
+  __device__ void ops(bf16x8 (&b)[RT / 2]) const {
+#pragma unroll
+    for (int kb = 0; kb < RT / 2; ++kb)
+      b[kb] = __builtin_bit_cast(bf16x8, u32x4{p[2 * kb][0], p[2 * kb][1], p[2 * kb + 1][0], p[2 * kb + 1][1]});
+  }
+  // bf16(d) where the activation h of the same row is > 0, else 0 (the ReLU
+  // derivative). h holds ReLU outputs, so its halves are non-negative
+  // integers: min(h, 1) is the 0/1 indicator and a 16-bit multiply applies it.
+  __device__ void masked(const float (&d)[RT][4], const Pk& h) {
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const bf16x2 v = __builtin_convertvector((f32x2){d[mt][2 * k], d[mt][2 * k + 1]}, bf16x2);
+        const u16x2 ind = __builtin_elementwise_min(__builtin_bit_cast(u16x2, h.p[mt][k]), (u16x2)1);
+        p[mt][k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, v) * ind);
+      }
+  }
+  // write row tiles [MT0, MT0 + NMT) of the block into a [row][vertex]
+  // staging buffer (as its rows 0 ..) at vertex column wave*16
+  template <int SP, int MT0 = 0, int NMT = RT>
+  __device__ void stage(__bf16* buf, int wave, int lane) const {
+    const int g = lane >> 4, c = lane & 15;
+    unsigned short* b = reinterpret_cast<unsigned short*>(buf) + 4 * g * SP + wave * 16 + c;
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        b[(mt * 16 + 2 * k) * SP] = (unsigned short)(p[MT0 + mt][k] & 0xffffu);
+        b[(mt * 16 + 2 * k + 1) * SP] = (unsigned short)(p[MT0 + mt][k] >> 16);
+      }
+  }
+};
+
 // Stage order of one tile's forward: layer 0, hidden layers 1..NH-1, output
 // rows [0, 4K) and [4K, 8K); stage s computes from buffer s % 2 while stage
 // s + 1 is copied into the other. With NH even the stage after the forward
@@ -56,55 +110,61 @@ struct NetBf16 {
     sync_stage();
   }
 
-  // Forward of one tile with layer 0 resident in b0; leaves `next` (elems)
-  // in b0 when it returns.
-  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&h)[NH][MTH][4],
-                                 float (&out)[MTO][4], const W* next, int next_elems, int lane) {
+  // Hidden layers of one tile with layer 0 resident in b0: hp[l] receives
+  // hidden layer l's activations as B operands; `next` (elems) is in b0 on
+  // return (a full forward puts the output layer's first half there).
+  __device__ static void hidden(const W* wg, W* b0, W* b1, const typename M::Input& x, Pk<MTH> (&hp)[NH],
+                                const W* next, int next_elems, int lane) {
     const Bf16Layout Lt = layout();
+    float y[MTH][4];
+    bf16x8 b[M::KBH];
     dma(b1, wg + Lt.fwd_off(1), H * H);
-    M::layer0(b0, x, h[0], lane);
+    M::layer0_linear(b0, x, y, lane);
+    M::relu_operands(y, b);
+    hp[0].from_ops(b);
     sync_stage();
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
       W* cur = (l & 1) ? b1 : b0;
       W* oth = (l & 1) ? b0 : b1;
       if (l + 1 < NH) dma(oth, wg + Lt.fwd_off(l + 1), H * H);
-      else dma(oth, wg + Lt.fwd_off(NH), HALF_O * 16 * H);
-      float y[MTH][4];
-      M::template gemm<MTH>(cur, h[l - 1], y, lane);
-#pragma unroll
-      for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h[l][mt][i] = relu(y[mt][i]);
+      else dma(oth, next, next_elems);
+      M::template gemm_op<MTH>(cur, b, y, lane);
+      M::relu_operands(y, b);
+      hp[l].from_ops(b);
       sync_stage();
     }
-    // output rows, half 0 in b0 and half 1 in b1
+  }
+
+  // Full forward of one tile with layer 0 resident in b0; the next tile's
+  // layer 0 is resident in b0 on return (query, gradient).
+  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&out)[MTO][4],
+                                 int lane) {
+    const Bf16Layout Lt = layout();
+    Pk<MTH> hp[NH];
+    hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), HALF_O * 16 * H, lane);   // output half 0 -> b0
+    bf16x8 b[M::KBH];
+    hp[NH - 1].ops(b);
     dma(b1, wg + Lt.fwd_off(NH) + HALF_O * 16 * H, HALF_O * 16 * H);
     {
       float part[HALF_O][4];
-      M::template gemm<HALF_O>(b0, h[NH - 1], part, lane);
+      M::template gemm_op<HALF_O>(b0, b, part, lane);
 #pragma unroll
       for (int mt = 0; mt < HALF_O; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[mt][i] = part[mt][i];
     }
     sync_stage();
-    dma(b0, next, next_elems);
+    dma(b0, wg + Lt.fwd_off(0), H * 16);
     {
       float part[HALF_O][4];
-      M::template gemm<HALF_O>(b1, h[NH - 1], part, lane);
+      M::template gemm_op<HALF_O>(b1, b, part, lane);
 #pragma unroll
       for (int mt = 0; mt < HALF_O; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) out[HALF_O + mt][i] = part[mt][i];
     }
     sync_stage();
-  }
-
-  // Forward that leaves the next tile's layer 0 in b0 (query, gradient).
-  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&h)[NH][MTH][4],
-                                 float (&out)[MTO][4], int lane) {
-    forward(wg, b0, b1, x, h, out, wg + layout().fwd_off(0), H * 16, lane);
   }
 };
 
@@ -165,6 +225,12 @@ struct NetF32 {
     }
   }
 
+  __device__ static void forward(const W* wg, W* buf, W* unused, const typename M::Input& x, float (&out)[MTO][4],
+                                 int lane) {
+    float h[NH][MTH][4];
+    forward(wg, buf, unused, x, h, out, lane);
+  }
+
   __device__ static void forward(const W* wg, W* buf, W*, const typename M::Input& x, float (&h)[NH][MTH][4],
                                  float (&out)[MTO][4], int lane) {
     wstage(buf, wg + layout().off(0), H * P0);
@@ -214,30 +280,10 @@ struct NetF32 {
 template <int H, int K, int PREC>
 using LargeNet = typename std::conditional<PREC == 1, NetBf16<H, K>, NetF32<H, K>>::type;
 
-// Hidden activations kept by the backward kernels: BF16 pairs for the BF16
-// network (used only as BF16 staging operands and as ReLU masks h > 0),
-// FP32 otherwise.
+// Hidden activations kept by the FP32 backward kernels (the BF16 ones keep
+// them packed, as Pk).
 template <int PREC, int MTH>
 struct Act;
-
-template <int MTH>
-struct Act<1, MTH> {
-  uint32_t p[MTH][2];
-  __device__ void set(const float (&h)[MTH][4]) {
-#pragma unroll
-    for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const uint32_t lo = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k]);
-        const uint32_t hi = __builtin_bit_cast(unsigned short, (__bf16)h[mt][2 * k + 1]);
-        p[mt][k] = lo | (hi << 16);
-      }
-  }
-  __device__ float get(int mt, int i) const {
-    const uint32_t w = p[mt][i >> 1];
-    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
-  }
-};
 
 template <int MTH>
 struct Act<0, MTH> {
@@ -355,9 +401,8 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
     const int64_t v = tile * kWGV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    float h[N::NH][N::MTH][4];
     float out[N::MTO][4];
-    N::forward(wg, b0, b1, x, h, out, lane);
+    N::forward(wg, b0, b1, x, out, lane);
     if (MODE == 1) {
       if (valid) {
 #pragma unroll
@@ -425,9 +470,8 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
       vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
       wj = a.w[v];
     }
-    float h[N::NH][N::MTH][4];
     float out[MTO][4];
-    N::forward(wg, b0, b1, x, h, out, lane);
+    N::forward(wg, b0, b1, x, out, lane);
     {
       const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
@@ -456,24 +500,32 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
 }
 
 // ------------------------------------------------------- backward, BF16 ----
-// GROUP 0: weight gradients of the output layer and the last hidden layer;
-// GROUP 1: of hidden layers NH-2 .. 1 and layer 0. Each continues the
-// forward's weight pipeline through its dgrad stages and ends a tile with
-// the next tile's layer 0 resident.
+// Eight waves (two per SIMD) over 128-vertex tiles: each wave recomputes the
+// hidden layers and runs dgrad for its 16 vertices, and owns row tile `wave`
+// (and wave + 8 of the output layer) of every weight gradient it
+// accumulates. GROUP 0: the output layer and the last hidden layer; GROUP 1:
+// hidden layers NH-2 .. 1 and layer 0. The weight pipeline continues from
+// the hidden layers through the dgrad stages and ends a tile with the next
+// tile's layer 0 resident.
+constexpr int kBwdWaves = 8;
+constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
+constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
+
 template <int H, int K, int GROUP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bwd_bf16_kernel(LargeTrainArgs a) {
   typedef NetBf16<H, K> N;
   typedef typename N::M M;
   typedef __bf16 W;
   typedef __bf16 S;
-  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, SP = N::SP, KBO = N::KBO;
-  constexpr int RTW_H = (MTH + 3) / 4, RTW_O = (MTO + 3) / 4, CTH = H / 16, HALF_H = MTH / 2;
+  constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, KBO = N::KBO, SP = kBwdSP;
+  constexpr int CTH = H / 16, HALF_H = MTH / 2, KBH = MTH / 2;
+  static_assert(MTH == kBwdWaves && MTO == 2 * kBwdWaves, "one hidden row tile per wave");
   extern __shared__ __align__(16) unsigned char smem[];
   W* bufA = reinterpret_cast<W*>(smem);
   W* bufB = bufA + N::BUF;
-  S* dst = reinterpret_cast<S*>(smem + 2 * N::BUF * sizeof(W));
-  S* hst = dst + N::RMAX * SP;
+  S* dst = reinterpret_cast<S*>(smem + 2 * N::BUF * sizeof(W));   // [H rows][SP]
+  S* hst = dst + H * SP;                                           // [H rows][SP]
   const W* wg = reinterpret_cast<const W*>(a.wpack);
   const Bf16Layout Lt = N::layout();
   const NetDims dims{H, NH, K};
@@ -481,71 +533,60 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
+  const int rt[1] = {wave};                 // this wave's row tile (+ MTH for the output layer's 2nd half)
+  const int rt_hi[1] = {wave + MTH};
 
-  int rt_h[RTW_H], rt_o[RTW_O];
-  int nrt_h = 0, nrt_o = 0;
-#pragma unroll
-  for (int r = 0; r < RTW_H; ++r) { rt_h[r] = wave + 4 * r; if (rt_h[r] < MTH) nrt_h = r + 1; }
-#pragma unroll
-  for (int r = 0; r < RTW_O; ++r) { rt_o[r] = wave + 4 * r; if (rt_o[r] < MTO) nrt_o = r + 1; }
-
-  constexpr int NO = GROUP == 0 ? RTW_O : 1;        // output layer (group 0)
+  constexpr int NO = GROUP == 0 ? 2 : 1;            // output layer halves (group 0)
   constexpr int NM = GROUP == 1 ? NH - 2 : 1;       // hidden layers NH-2..1 (group 1)
-  f32x4 accO[NO][CTH];
-  f32x4 accT[RTW_H][CTH];                           // layer NH-1 (group 0)
-  f32x4 accM[NM][RTW_H][CTH];
-  f32x4 acc0[RTW_H][1];                             // layer 0 (group 1)
+  f32x4 accO[NO][1][CTH];
+  f32x4 accT[1][CTH];                               // layer NH-1 (group 0)
+  f32x4 accM[NM][1][CTH];
+  f32x4 acc0[1][1];                                 // layer 0 (group 1)
+  acc0[0][0] = zero4();
 #pragma unroll
-  for (int r = 0; r < RTW_H; ++r) {
-    acc0[r][0] = zero4();
+  for (int ct = 0; ct < CTH; ++ct) {
+    accT[0][ct] = zero4();
 #pragma unroll
-    for (int ct = 0; ct < CTH; ++ct) {
-      accT[r][ct] = zero4();
+    for (int l = 0; l < NM; ++l) accM[l][0][ct] = zero4();
 #pragma unroll
-      for (int l = 0; l < NM; ++l) accM[l][r][ct] = zero4();
-    }
+    for (int h = 0; h < NO; ++h) accO[h][0][ct] = zero4();
   }
-#pragma unroll
-  for (int r = 0; r < NO; ++r)
-#pragma unroll
-    for (int ct = 0; ct < CTH; ++ct) accO[r][ct] = zero4();
 
   W* b0 = bufA;
   W* b1 = bufB;
   N::begin(wg, b0);
-  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
+  const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t v = tile * kWGV + wave * 16 + c;
+    const int64_t v = tile * kBwdV + wave * 16 + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    Act<1, MTH> hp[NH];
-    {
-      float h[NH][MTH][4];
-      float out[MTO][4];
-      N::forward(wg, b0, b1, x, h, out, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
-#pragma unroll
-      for (int l = 0; l < NH; ++l) hp[l].set(h[l]);
-    }
+    Pk<MTH> hp[NH];
+    N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
     bf16x8 bo[KBO];
-    DOut<K, 1>::load_operands(a.dout, tile * 4 + wave, bo, lane);
+    DOut<K, 1>::load_operands(a.dout, tile * kBwdWaves + wave, bo, lane);
     float dh[MTH][4];
+    Pk<MTH> dhw;
     if constexpr (GROUP == 0) {
-      float dl[MTO][4];
-      DOut<K, 1>::load(a.dout, tile * 4 + wave, dl, lane);
-      stage_rows<S, MTO, SP>(dst, dl, wave, lane);
-      stage_act<S, 1, MTH, SP>(hst, hp[NH - 1], wave, lane);
+      Pk<MTO> dlw;
+      dlw.from_ops(bo);
+      dlw.template stage<SP, 0, MTH>(dst, wave, lane);           // output rows [0, 8K/2)
+      hp[NH - 1].template stage<SP>(hst, wave, lane);
       N::dma(b1, out_bwd + N::OB_HALF, N::OB_HALF);
       dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
-      N::sync_stage();                                  // also publishes the staging
-      wgrad_tiles<1, S, SP, RTW_O, CTH>(dst, hst, rt_o, nrt_o, accO, lane);
-      N::dma(b0, wg + Lt.fwd_off(0), H * 16);           // the next tile's layer 0
+      N::sync_stage();                                            // also publishes the staging
+      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[0], lane);
+      N::dma(b0, wg + Lt.fwd_off(0), H * 16);                     // the next tile's layer 0
       dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
-      mask_relu<1, MTH>(dh, hp[NH - 1]);
-      N::sync_stage();                                  // the staging has been read
-      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
-      stage_act<S, 1, MTH, SP>(hst, hp[NH - 2], wave, lane);
+      dhw.masked(dh, hp[NH - 1]);
+      N::sync_stage();                                            // the first half has been read
+      dlw.template stage<SP, MTH, MTH>(dst, wave, lane);          // output rows [8K/2, 8K)
       __syncthreads();
-      wgrad_tiles<1, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accT, lane);
+      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[1], lane);
+      __syncthreads();
+      dhw.template stage<SP>(dst, wave, lane);
+      hp[NH - 2].template stage<SP>(hst, wave, lane);
+      __syncthreads();
+      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accT, lane);
       // the next writes to the staging area follow the next tile's forward,
       // whose barriers order them after these reads
     } else {
@@ -554,37 +595,42 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
       N::sync_stage();
       N::dma(b0, wg + Lt.bwd_off(NH - 1), H * H);
       dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
-      mask_relu<1, MTH>(dh, hp[NH - 1]);
+      dhw.masked(dh, hp[NH - 1]);
       N::sync_stage();
-      float d2[MTH][4];
-      N::dma(b1, wg + Lt.bwd_off(NH - 2), H * H);
-      dgrad<H, K, 1, MTH>(b0, dh, d2, lane);             // through hidden layer NH-1
-      mask_relu<1, MTH>(d2, hp[NH - 2]);
-      N::sync_stage();
+      Pk<MTH> d2w;
+      {
+        bf16x8 op[KBH];
+        dhw.ops(op);
+        float d2[MTH][4];
+        N::dma(b1, wg + Lt.bwd_off(NH - 2), H * H);
+        dgrad_rows<KBH, MTH, 0>(b0, op, d2, lane);                // through hidden layer NH-1
+        d2w.masked(d2, hp[NH - 2]);
+        N::sync_stage();
+      }
       W* cur = b1;   // holds hidden layer l's backward fragments
       W* oth = b0;
 #pragma unroll
       for (int l = NH - 2; l >= 1; --l) {
-        stage_rows<S, MTH, SP>(dst, d2, wave, lane);
-        stage_act<S, 1, MTH, SP>(hst, hp[l - 1], wave, lane);
+        d2w.template stage<SP>(dst, wave, lane);
+        hp[l - 1].template stage<SP>(hst, wave, lane);
         if (l > 1) N::dma(oth, wg + Lt.bwd_off(l - 1), H * H);
-        else N::dma(oth, wg + Lt.fwd_off(0), H * 16);   // the next tile's layer 0
+        else N::dma(oth, wg + Lt.fwd_off(0), H * 16);             // the next tile's layer 0
+        bf16x8 op[KBH];
+        d2w.ops(op);
         float dn[MTH][4];
-        dgrad<H, K, 1, MTH>(cur, d2, dn, lane);
-        mask_relu<1, MTH>(dn, hp[l - 1]);
-        N::sync_stage();                                // also publishes the staging
-        wgrad_tiles<1, S, SP, RTW_H, CTH>(dst, hst, rt_h, nrt_h, accM[l - 1], lane);
+        dgrad_rows<KBH, MTH, 0>(cur, op, dn, lane);
+        Pk<MTH> dnw;
+        dnw.masked(dn, hp[l - 1]);
+        N::sync_stage();                                          // also publishes the staging
+        wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accM[l - 1], lane);
         __syncthreads();
-#pragma unroll
-        for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) d2[mt][i] = dn[mt][i];
+        d2w = dnw;
         W* t = cur; cur = oth; oth = t;
       }
-      stage_rows<S, MTH, SP>(dst, d2, wave, lane);
+      d2w.template stage<SP>(dst, wave, lane);
       stage_input<S, SP>(hst, a.feat, a.ld, v, valid, wave, lane);
       __syncthreads();
-      wgrad_tiles<1, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      wgrad_tiles<1, S, SP, 1, 1, kBwdV>(dst, hst, rt, 1, acc0, lane);
       b0 = cur;   // the next tile's layer 0
       b1 = oth;
     }
@@ -592,12 +638,13 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
 
   float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
   if constexpr (GROUP == 0) {
-    flush_tiles<RTW_O, CTH>(part, dims, NH, rt_o, nrt_o, accO, lane);
-    flush_tiles<RTW_H, CTH>(part, dims, NH - 1, rt_h, nrt_h, accT, lane);
+    flush_tiles<1, CTH>(part, dims, NH, rt, 1, accO[0], lane);
+    flush_tiles<1, CTH>(part, dims, NH, rt_hi, 1, accO[1], lane);
+    flush_tiles<1, CTH>(part, dims, NH - 1, rt, 1, accT, lane);
   } else {
 #pragma unroll
-    for (int l = 1; l <= NH - 2; ++l) flush_tiles<RTW_H, CTH>(part, dims, l, rt_h, nrt_h, accM[l - 1], lane);
-    flush_tiles<RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
+    for (int l = 1; l <= NH - 2; ++l) flush_tiles<1, CTH>(part, dims, l, rt, 1, accM[l - 1], lane);
+    flush_tiles<1, 1>(part, dims, 0, rt, 1, acc0, lane);
   }
 }
 
@@ -727,7 +774,9 @@ template <int H, int K, int PREC>
 struct LargeLds {
   typedef LargeNet<H, K, PREC> N;
   static constexpr size_t fwd = (size_t)(PREC == 1 ? 2 : 1) * N::BUF * sizeof(typename N::W);
-  static constexpr size_t bwd = fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
+  static constexpr size_t bwd = PREC == 1 ? fwd + (size_t)2 * H * kBwdSP * sizeof(__bf16)
+                                          : fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
+  static constexpr int bwd_threads = PREC == 1 ? 64 * kBwdWaves : 256;
   static_assert(bwd <= 160 * 1024, "LDS budget");
 };
 
@@ -770,8 +819,9 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
     attr = true;
   }
   hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), sh_fwd, st, a);
-  hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(256), sh_bwd, st, a);
-  hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(256), sh_bwd, st, a);
+  const int bt = LargeLds<H, K, PREC>::bwd_threads;
+  hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+  hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
   return hipGetLastError();
 }
 
