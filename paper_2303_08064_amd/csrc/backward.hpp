@@ -106,6 +106,91 @@ __device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const in
   }
 }
 
+// Ownership of a layer's dW tiles (RT row tiles x CT column tiles) among the
+// NW waves of a workgroup, tile j of a wave being (rt(w, j), ct(w, j)):
+// * RT >= NW (row mode): wave w owns row tiles w, w + NW, ... and every
+//   column tile (per staged block: CT column operands, one row operand per
+//   row tile);
+// * RT < NW (column mode, NW a multiple of CT): wave w owns column tile
+//   w % CT and row tiles w / CT + (NW / CT) j below RT (one column operand,
+//   one row operand per tile).
+template <int RT, int CT, int NW>
+struct Own {
+  static constexpr bool ROW = RT >= NW;
+  static_assert(ROW || NW % CT == 0, "waves must split evenly over the column tiles");
+  static constexpr int STEP = ROW ? NW : NW / CT;
+  static constexpr int NRW = (RT + STEP - 1) / STEP;        // row tiles per wave
+  static constexpr int TPW = ROW ? NRW * CT : NRW;          // tiles per wave
+  __device__ static int rt(int wave, int j) { return ROW ? wave + NW * (j / CT) : wave / CT + STEP * j; }
+  __device__ static int ct(int wave, int j) { return ROW ? j % CT : wave % CT; }
+};
+
+template <int PREC, typename S, int SP>
+__device__ __forceinline__ auto stage_operand(const S* st, int row, int vb, int g, int c) {
+  if constexpr (PREC == 1) return *reinterpret_cast<const bf16x8*>(st + (row * 16 + c) * SP + vb * 32 + 8 * g);
+  else return st[(row * 16 + c) * SP + vb * 4 + g];
+}
+
+// acc[j] += D[rows of rt(j)][v] * Hs[cols of ct(j)][v]^T over NV staged vertices
+template <int PREC, typename S, int SP, int RT, int CT, int NW, int NV>
+__device__ __forceinline__ void wgrad_own(const S* dst, const S* hst, f32x4 (&acc)[Own<RT, CT, NW>::TPW],
+                                          int wave, int lane) {
+  typedef Own<RT, CT, NW> O;
+  typedef decltype(stage_operand<PREC, S, SP>(dst, 0, 0, 0, 0)) Op;
+  const int g = lane >> 4, c = lane & 15;
+  constexpr int VB = PREC == 1 ? NV / 32 : NV / 4;
+#pragma unroll
+  for (int vb = 0; vb < VB; ++vb) {
+    if constexpr (O::ROW) {
+      Op hb[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) hb[ct] = stage_operand<PREC, S, SP>(hst, ct, vb, g, c);
+#pragma unroll
+      for (int r = 0; r < O::NRW; ++r) {
+        if (O::rt(wave, r * CT) < RT) {
+          const Op da = stage_operand<PREC, S, SP>(dst, O::rt(wave, r * CT), vb, g, c);
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            if constexpr (PREC == 1) acc[r * CT + ct] = mfma_bf16_32(da, hb[ct], acc[r * CT + ct]);
+            else acc[r * CT + ct] = mfma_f32_4(da, hb[ct], acc[r * CT + ct]);
+          }
+        }
+      }
+    } else {
+      const Op hb = stage_operand<PREC, S, SP>(hst, O::ct(wave, 0), vb, g, c);
+#pragma unroll
+      for (int j = 0; j < O::TPW; ++j) {
+        if (O::rt(wave, j) < RT) {
+          const Op da = stage_operand<PREC, S, SP>(dst, O::rt(wave, j), vb, g, c);
+          if constexpr (PREC == 1) acc[j] = mfma_bf16_32(da, hb, acc[j]);
+          else acc[j] = mfma_f32_4(da, hb, acc[j]);
+        }
+      }
+    }
+  }
+}
+
+// Flush a wave's owned dW tiles of layer l to the workgroup's canonical partial.
+template <int RT, int CT, int NW>
+__device__ __forceinline__ void flush_own(float* part, const NetDims& d, int l,
+                                          const f32x4 (&acc)[Own<RT, CT, NW>::TPW], int wave, int lane) {
+  typedef Own<RT, CT, NW> O;
+  const int g = lane >> 4, c = lane & 15;
+  const int cols = d.cols(l);
+  const int64_t off = d.canon_off(l);
+#pragma unroll
+  for (int j = 0; j < O::TPW; ++j) {
+    const int k = O::ct(wave, j) * 16 + c;
+    if (O::rt(wave, j) >= RT || k >= cols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int R = O::rt(wave, j) * 16 + 4 * g + i;
+      const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
+      part[off + (int64_t)n * cols + k] = acc[j][i];
+    }
+  }
+}
+
 // Flush a wave's dW tiles of layer l to the workgroup's canonical partial.
 template <int NR, int NC>
 __device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,

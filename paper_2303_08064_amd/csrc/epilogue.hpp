@@ -82,9 +82,18 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
 #pragma unroll
     for (int p = 0; p < 7; ++p) {
       const int t = p * KQ + q;
-      dl[t >> 2][t & 3] = fsel(sc == 0.0f, 0.0f, dl[t >> 2][t & 3] * sc);   // no 0 * inf
+      dl[t >> 2][t & 3] *= sc;
     }
     dl[t7 >> 2][t7 & 3] = gs * (r - Aq);
+  }
+  // padding lanes (a branch taken only in a batch's last tile): zeroed
+  // outright, so that no non-finite partial of their arbitrary lobes reaches
+  // the weight gradient as 0 * inf
+  if (!valid) {
+#pragma unroll
+    for (int mt = 0; mt < MTO; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dl[mt][i] = 0.0f;
   }
   return logq;
 }

@@ -56,19 +56,6 @@ __device__ __forceinline__ float log1pf_(float y) {
   return fsel(fabsf(y) < 0.0625f, log1p_series(y), flog(1.0f + y));
 }
 
-// tanh(o/2) = 2 sigmoid(o) - 1 (Tab. "decoding") as m/(2 - m) with m = 1 - e^{-|o|},
-// keeping m accurate for small |o|. Returns d; also e = e^{-|o|} and r = 1/(1+e).
-struct Half {
-  float d, e, r;
-};
-__device__ __forceinline__ Half decode_unit(float o) {
-  float ao = fabsf(o);
-  float m = -expm1f_(-ao);
-  float e = 1.0f - m;
-  float r = frcp(2.0f - m);
-  return {copysignf(m * r, o), e, r};
-}
-
 // Decoded lobe: orthonormal frame, sharpness, eccentricity, log normaliser.
 struct Lobe {
   float zx, zy, zz, xx, xy, xz;
@@ -84,6 +71,7 @@ struct LobeAux {
   float loglam, loga;       // clamped raw values
   bool lam_in, a_in;        // raw values inside the clamp range
   float logK;
+  float qlam;               // 2 lam / expm1(2 lam)
 };
 
 // A (cos, sin) pair divided by its norm; a zero pair becomes (1, 0).
@@ -102,23 +90,50 @@ __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a
   return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
 }
 
+// The same, also returning 2 lam / expm1(2 lam) = 2 lam e^{-2 lam} / (1 - e^{-2 lam})
+// (the normaliser's lambda derivative) from the same exponential.
+__device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps, float& qlam) {
+  const float x = -2.0f * lam;
+  const float ex = fexp(x);                           // e^{-2 lam}
+  float p = fmaf(x, 1.0f / 120.0f, 1.0f / 24.0f);    // expm1 series, as in expm1f_
+  p = fmaf(x, p, 1.0f / 6.0f);
+  p = fmaf(x, p, 0.5f);
+  p = fmaf(x, p, 1.0f);
+  p = p * x;
+  const float one_m = -fsel(fabsf(x) < 0.125f, p, ex - 1.0f);   // 1 - e^{-2 lam}
+  qlam = -x * ex * frcp(one_m);                       // -> 0 as e^{-2 lam} underflows
+  return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
+}
+
 // Raw outputs o[0..7] of one lobe -> frame, lambda, a, log K (Tab. "decoding",
 // Sec. 4.1 Euler frame). Pair normalisation and the clamp are this library's
 // readings of the paper.
+//
+// cos(theta) = tanh(o0/2) needs absolute accuracy only; a sin/cos pair needs
+// the ratio of its two tanh(o/2) = m/(2 - m) values (m = 1 - e^{-|o|}, kept
+// accurate for small |o|), which the pair (m2 (2 - m1), m1 (2 - m2)) has
+// without a division; one reciprocal R = 1/((2 - m1)(2 - m2)) per pair then
+// gives the tanh' factors 2 e_i/(2 - m_i)^2 and the pair's norm.
+__device__ __forceinline__ void decode_pair(float oc, float os, float& cu, float& su, float& inv_n, float& hc,
+                                            float& hs) {
+  const float mc = -expm1f_(-fabsf(oc)), ms = -expm1f_(-fabsf(os));
+  const float tc = 2.0f - mc, ts = 2.0f - ms;
+  const float R = frcp(tc * ts);
+  float inv;
+  unit_pair(copysignf(mc * ts, oc), copysignf(ms * tc, os), cu, su, inv);
+  inv_n = tc * ts * inv;                             // 1/|(tanh(oc/2), tanh(os/2))|
+  const float rc = ts * R, rs = tc * R;              // 1/(2 - mc), 1/(2 - ms)
+  hc = 2.0f * (1.0f - mc) * rc * rc;
+  hs = 2.0f * (1.0f - ms) * rs * rs;
+}
+
 __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X) {
-  Half h0 = decode_unit(o[0]);
-  Half h1 = decode_unit(o[1]);
-  Half h2 = decode_unit(o[2]);
-  Half h3 = decode_unit(o[3]);
-  Half h4 = decode_unit(o[4]);
-  X.ct = h0.d;
-  X.st = 2.0f * fsqrt(h0.e) * h0.r;     // sech(o/2) = sqrt(1 - tanh^2)
-  X.h1 = 2.0f * h1.e * h1.r * h1.r;
-  X.h2 = 2.0f * h2.e * h2.r * h2.r;
-  X.h3 = 2.0f * h3.e * h3.r * h3.r;
-  X.h4 = 2.0f * h4.e * h4.r * h4.r;
-  unit_pair(h2.d, h1.d, X.cp, X.sp, X.inv_np);
-  unit_pair(h4.d, h3.d, X.ctau, X.stau, X.inv_nt);
+  const float e0 = fexp(-fabsf(o[0]));
+  const float r0 = frcp(1.0f + e0);
+  X.ct = copysignf((1.0f - e0) * r0, o[0]);
+  X.st = 2.0f * fsqrt(e0) * r0;                      // sech(o/2) = sqrt(1 - tanh^2)
+  decode_pair(o[2], o[1], X.cp, X.sp, X.inv_np, X.h2, X.h1);
+  decode_pair(o[4], o[3], X.ctau, X.stau, X.inv_nt, X.h4, X.h3);
   L.zx = X.cp * X.st;
   L.zy = X.sp * X.st;
   L.zz = X.ct;
@@ -132,7 +147,7 @@ __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L
   X.loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
   L.lam = fexp(X.loglam);
   L.a = fexp(X.loga);
-  X.logK = log_normaliser(L.lam, X.loglam, L.a, eps);
+  X.logK = log_normaliser(L.lam, X.loglam, L.a, eps, X.qlam);
   L.logc = 0.0f;
 }
 
@@ -269,9 +284,7 @@ __device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, c
   float epl = e.E + 1.0f;
   float twolam = 2.0f * L.lam;
   // log lambda
-  float q = twolam * frcp(expm1f_(twolam));     // 2 lam / expm1(2 lam); -> 0 for large lam
-  q = fsel(twolam > 80.0f, 0.0f, q);
-  g[5] = fsel(A.lam_in && live, gk * (twolam * e.E - q + 1.0f), 0.0f);
+  g[5] = fsel(A.lam_in && live, gk * (twolam * e.E - A.qlam + 1.0f), 0.0f);
   // log a
   float Dp = e.L * fmaf(twolam, epl, 1.0f);
   float ga = L.a * fmaf(e.c2, Dp, 0.5f * frcp(1.0f + eps + L.a));

@@ -2,12 +2,13 @@
 // NLL, closed-form NASG backward, MLP backward on MFMA; then a fixed-order
 // reduction of per-workgroup weight gradients and a fused Adam update.
 //
-// Work split of the fused kernel (one persistent workgroup of 4 waves per CU):
-// each wave runs forward, NASG backward and dgrad for its own 16 vertices with
-// activations in registers (nothing is written to HBM); for the weight
-// gradient dW_l = sum_v delta_l(v) h_{l-1}(v)^T the four waves stage delta_l
-// and h_{l-1} of the workgroup's 64 vertices in LDS and each wave accumulates
-// its own rows of dW_l in registers across every tile the workgroup visits.
+// Work split of the fused kernel (one persistent workgroup per CU; eight waves
+// over 128-vertex tiles in BF16, four over 64 in FP32): each wave runs
+// forward, NASG backward and dgrad for its own 16 vertices with activations
+// in registers (nothing is written to HBM); for the weight gradient
+// dW_l = sum_v delta_l(v) h_{l-1}(v)^T the waves stage delta_l and h_{l-1}
+// of the tile's vertices in LDS and each wave accumulates its own tiles of
+// dW_l in registers across every tile the workgroup visits.
 // Every sum has a fixed order, so results are bitwise reproducible.
 #include <type_traits>
 
@@ -19,6 +20,10 @@
 namespace nasg {
 
 
+// waves per training workgroup (see TrainCfg)
+template <int PREC>
+constexpr int train_waves() { return PREC == 1 ? 8 : 4; }
+
 template <int H, int K, int PREC>
 struct TrainCfg {
   typedef Mlp<H, K, PREC> M;
@@ -26,11 +31,16 @@ struct TrainCfg {
   static constexpr int NHMAX = 4;
   static constexpr int KQ = K / 4;
   static constexpr int MTH = H / 16, MTO = K / 2;
-  static constexpr int RMAX = (8 * K > H) ? 8 * K : H;   // rows of the largest delta
-  static constexpr int SP = PREC == 1 ? kWGV + 8 : kWGV + 4;   // staging pitch (elements)
-  static constexpr int RTW_H = (MTH + 3) / 4;   // row tiles of dW per wave, hidden layers
-  static constexpr int RTW_O = (MTO + 3) / 4;   // row tiles of dW per wave, output layer
   static constexpr int CTH = H / 16;            // column tiles of dW (hidden input)
+  // BF16: eight waves (two per SIMD) over 128-vertex tiles; FP32 (larger
+  // weights and staging): four waves over 64-vertex tiles
+  static constexpr int NW = train_waves<PREC>();
+  static constexpr int NV = 16 * NW;            // vertices per tile
+  static constexpr int RMAX = (8 * K > H) ? 8 * K : H;   // rows of the largest delta
+  static constexpr int SP = PREC == 1 ? NV + 8 : NV + 4;   // staging pitch (elements)
+  typedef Own<MTH, 1, NW> O0;                   // layer 0
+  typedef Own<MTH, CTH, NW> OH;                 // hidden layers
+  typedef Own<MTO, CTH, NW> OO;                 // output layer
   static constexpr int stage_elems() { return (RMAX + H) * SP; }
 };
 
@@ -49,19 +59,22 @@ struct TrainLds {
 };
 
 template <int H, int K, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(64 * train_waves<PREC>())
+__attribute__((amdgpu_waves_per_eu(train_waves<PREC>() / 4, train_waves<PREC>() / 4)))
 void train_kernel(TrainArgs a) {
   typedef TrainCfg<H, K, PREC> C;
   typedef typename C::M M;
   typedef typename C::S S;
   typedef TrainLds<H, K, PREC> TL;
   typedef typename TL::W W;
-  constexpr int NHMAX = C::NHMAX, KQ = C::KQ, MTH = C::MTH, MTO = C::MTO, SP = C::SP;
+  constexpr int NHMAX = C::NHMAX, KQ = C::KQ, MTH = C::MTH, MTO = C::MTO, SP = C::SP, NW = C::NW, NV = C::NV;
+  constexpr int CTH = C::CTH;
   extern __shared__ __align__(16) unsigned char smem[];
   W* lds = reinterpret_cast<W*>(smem);
   S* dst = reinterpret_cast<S*>(smem + a.lds_bytes);     // delta staging [RMAX][SP]
   S* hst = dst + C::RMAX * SP;                            // input staging [H][SP]
-  block_copy_to_lds(lds, a.wpack, a.lds_bytes);
+  lds_dma(lds, a.wpack, a.lds_bytes);
+  lds_dma_wait();
   __syncthreads();
 
   const int lane = lane_id();
@@ -71,34 +84,22 @@ void train_kernel(TrainArgs a) {
   const NetDims dims{H, nh, K};
   const float inv_b = 1.0f / (float)a.B;
 
-  // this wave's dW row tiles per layer: rt = wave, wave + 4, ...
-  int rt_h[C::RTW_H], rt_o[C::RTW_O];
-  int nrt_h = 0, nrt_o = 0;
+  f32x4 acc0[C::O0::TPW];
+  f32x4 acch[NHMAX - 1][C::OH::TPW];
+  f32x4 acco[C::OO::TPW];
 #pragma unroll
-  for (int r = 0; r < C::RTW_H; ++r) { rt_h[r] = wave + 4 * r; if (rt_h[r] < MTH) nrt_h = r + 1; }
+  for (int j = 0; j < C::O0::TPW; ++j) acc0[j] = zero4();
 #pragma unroll
-  for (int r = 0; r < C::RTW_O; ++r) { rt_o[r] = wave + 4 * r; if (rt_o[r] < MTO) nrt_o = r + 1; }
-
-  f32x4 acc0[C::RTW_H][1];
-  f32x4 acch[NHMAX - 1][C::RTW_H][C::CTH];
-  f32x4 acco[C::RTW_O][C::CTH];
+  for (int l = 0; l < NHMAX - 1; ++l)
 #pragma unroll
-  for (int r = 0; r < C::RTW_H; ++r) {
-    acc0[r][0] = zero4();
+    for (int j = 0; j < C::OH::TPW; ++j) acch[l][j] = zero4();
 #pragma unroll
-    for (int l = 0; l < NHMAX - 1; ++l)
-#pragma unroll
-      for (int ct = 0; ct < C::CTH; ++ct) acch[l][r][ct] = zero4();
-  }
-#pragma unroll
-  for (int r = 0; r < C::RTW_O; ++r)
-#pragma unroll
-    for (int ct = 0; ct < C::CTH; ++ct) acco[r][ct] = zero4();
+  for (int j = 0; j < C::OO::TPW; ++j) acco[j] = zero4();
   double loss_sum = 0.0, w_sum = 0.0;
 
-  const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
+  const int64_t n_tiles = (a.B + NV - 1) / NV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t v = tile * kWGV + wave * 16 + c;
+    const int64_t v = tile * NV + wave * 16 + c;
     const bool valid = v < a.B;
     // ---- forward (recomputed) ----
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
@@ -134,7 +135,7 @@ void train_kernel(TrainArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
       __syncthreads();
-      wgrad_tiles<PREC, S, SP, C::RTW_O, C::CTH>(dst, hst, rt_o, nrt_o, acco, lane);
+      wgrad_own<PREC, S, SP, MTO, CTH, NW, NV>(dst, hst, acco, wave, lane);
       __syncthreads();
     }
     // ---- hidden layers l = nh-1 .. 1 ----
@@ -155,7 +156,7 @@ void train_kernel(TrainArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dn[mt][i] = prev[mt][i] > 0.0f ? dn[mt][i] : 0.0f;
       __syncthreads();
-      wgrad_tiles<PREC, S, SP, C::RTW_H, C::CTH>(dst, hst, rt_h, nrt_h, acch[l - 1], lane);
+      wgrad_own<PREC, S, SP, MTH, CTH, NW, NV>(dst, hst, acch[l - 1], wave, lane);
       __syncthreads();
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
@@ -177,21 +178,21 @@ void train_kernel(TrainArgs a) {
         hst[k * SP + wave * 16 + c] = (S)xv;
       }
       __syncthreads();
-      wgrad_tiles<PREC, S, SP, C::RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
+      wgrad_own<PREC, S, SP, MTH, 1, NW, NV>(dst, hst, acc0, wave, lane);
       __syncthreads();
     }
   }
 
   // ---- flush this workgroup's partial sums ----
   float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
-  flush_tiles<C::RTW_H, 1>(part, dims, 0, rt_h, nrt_h, acc0, lane);
+  flush_own<MTH, 1, NW>(part, dims, 0, acc0, wave, lane);
 #pragma unroll
   for (int l = 1; l < NHMAX; ++l)
-    if (l < nh) flush_tiles<C::RTW_H, C::CTH>(part, dims, l, rt_h, nrt_h, acch[l - 1], lane);
-  flush_tiles<C::RTW_O, C::CTH>(part, dims, nh, rt_o, nrt_o, acco, lane);
+    if (l < nh) flush_own<MTH, CTH, NW>(part, dims, l, acch[l - 1], wave, lane);
+  flush_own<MTO, CTH, NW>(part, dims, nh, acco, wave, lane);
 
-  // loss partials: wave reduction, then the four waves in order
-  __shared__ double red[4][2];
+  // loss partials: wave reduction, then the waves in order
+  __shared__ double red[NW][2];
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
     loss_sum += __shfl_xor(loss_sum, s);
@@ -200,8 +201,11 @@ void train_kernel(TrainArgs a) {
   if (lane == 0) { red[wave][0] = loss_sum; red[wave][1] = w_sum; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    a.loss_partial[2 * blockIdx.x] = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
-    a.loss_partial[2 * blockIdx.x + 1] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    double ls = 0.0, ws = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) { ls += red[w][0]; ws += red[w][1]; }
+    a.loss_partial[2 * blockIdx.x] = ls;
+    a.loss_partial[2 * blockIdx.x + 1] = ws;
   }
 }
 
@@ -214,15 +218,20 @@ int train_workgroups(int64_t B, int num_cus) {
 template <int H, int K, int PREC>
 static hipError_t launch_train_t(const TrainArgs& a, int n_wg, hipStream_t st) {
   typedef TrainCfg<H, K, PREC> C;
-  size_t shmem = (size_t)a.lds_bytes + sizeof(typename C::S) * C::stage_elems();
+  const size_t stage = sizeof(typename C::S) * C::stage_elems();
+  const size_t shmem = (size_t)a.lds_bytes + stage;
   auto kern = train_kernel<H, K, PREC>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    // the largest footprint of this network shape (4 hidden layers)
+    const NetDims d{H, C::NHMAX, K};
+    const size_t wmax = PREC == 1 ? (size_t)Bf16Layout{d}.total_elems() * 2 : (size_t)F32Layout{d}.total_elems() * 4;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(wmax + stage));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(n_wg), dim3(256), shmem, st, a);
+  hipLaunchKernelGGL(kern, dim3(n_wg), dim3(64 * C::NW), shmem, st, a);
   return hipGetLastError();
 }
 
