@@ -317,7 +317,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   unsigned char* ws = static_cast<unsigned char*>(s.workspace);
   const int n_wg = train_workgroups(B, ctx->num_cus);
   const bool large = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision);
-  const int n_loss = large ? gradout_workgroups(B, ctx->num_cus) : n_wg;
+  const int n_loss = large ? large_loss_workgroups(B, ctx->num_cus, ctx->cfg.precision) : n_wg;
   TrainArgs t;
   t.wpack = s.wpack;
   t.lds_bytes = (int)packed_bytes_of(&ctx->cfg);

@@ -179,8 +179,9 @@ hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st)
 // Query / train kernel grid bounds (workgroups) for a batch of B vertices.
 constexpr int kMaxTrainWG = 256;
 int train_workgroups(int64_t B, int num_cus);
-// the large network's gradient kernel: up to two workgroups per CU
-int gradout_workgroups(int64_t B, int num_cus);
+// loss partials the large network's training writes (the workgroups of the
+// kernel that evaluates the loss)
+int large_loss_workgroups(int64_t B, int num_cus, int prec);
 int reduce_blocks(int64_t n_weights);
 
 }  // namespace nasg

@@ -136,15 +136,13 @@ struct NetBf16 {
     }
   }
 
-  // Full forward of one tile with layer 0 resident in b0; the next tile's
-  // layer 0 is resident in b0 on return (query, gradient).
-  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&out)[MTO][4],
-                                 int lane) {
+  // Output layer from the last hidden layer's activations, with its first
+  // half resident in b0; leaves `next` (elems) in b0 on return.
+  __device__ static void output(const W* wg, W* b0, W* b1, const Pk<MTH>& hl, float (&out)[MTO][4],
+                                const W* next, int next_elems, int lane) {
     const Bf16Layout Lt = layout();
-    Pk<MTH> hp[NH];
-    hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), HALF_O * 16 * H, lane);   // output half 0 -> b0
     bf16x8 b[M::KBH];
-    hp[NH - 1].ops(b);
+    hl.ops(b);
     dma(b1, wg + Lt.fwd_off(NH) + HALF_O * 16 * H, HALF_O * 16 * H);
     {
       float part[HALF_O][4];
@@ -155,7 +153,7 @@ struct NetBf16 {
         for (int i = 0; i < 4; ++i) out[mt][i] = part[mt][i];
     }
     sync_stage();
-    dma(b0, wg + Lt.fwd_off(0), H * 16);
+    dma(b0, next, next_elems);
     {
       float part[HALF_O][4];
       M::template gemm_op<HALF_O>(b1, b, part, lane);
@@ -165,6 +163,16 @@ struct NetBf16 {
         for (int i = 0; i < 4; ++i) out[HALF_O + mt][i] = part[mt][i];
     }
     sync_stage();
+  }
+
+  // Full forward of one tile with layer 0 resident in b0; the next tile's
+  // layer 0 is resident in b0 on return (query, gradient).
+  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&out)[MTO][4],
+                                 int lane) {
+    const Bf16Layout Lt = layout();
+    Pk<MTH> hp[NH];
+    hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), HALF_O * 16 * H, lane);   // output half 0 -> b0
+    output(wg, b0, b1, hp[NH - 1], out, wg + Lt.fwd_off(0), H * 16, lane);
   }
 };
 
@@ -503,10 +511,14 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
 // Eight waves (two per SIMD) over 128-vertex tiles: each wave recomputes the
 // hidden layers and runs dgrad for its 16 vertices, and owns row tile `wave`
 // (and wave + 8 of the output layer) of every weight gradient it
-// accumulates. GROUP 0: the output layer and the last hidden layer; GROUP 1:
-// hidden layers NH-2 .. 1 and layer 0. The weight pipeline continues from
-// the hidden layers through the dgrad stages and ends a tile with the next
-// tile's layer 0 resident.
+// accumulates. GROUP 1 (launched first) also runs the output layer and the
+// weighted-NLL / NASG backward (Sec. 4.2), stores dL/d(raw outputs) and the
+// loss partials, and accumulates the weight gradients of hidden layers
+// NH-2 .. 1 and layer 0; the VALU-heavy NASG work of one wave overlaps the
+// MFMA work of the other on each SIMD. GROUP 0 reads the stored gradient and
+// accumulates those of the output layer and the last hidden layer. The
+// weight pipeline runs through every stage of a tile and ends it with the
+// next tile's layer 0 resident.
 constexpr int kBwdWaves = 8;
 constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
 constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
@@ -552,6 +564,8 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
     for (int h = 0; h < NO; ++h) accO[h][0][ct] = zero4();
   }
 
+  const float inv_b = 1.0f / (float)a.B;
+  double loss_sum = 0.0, w_sum = 0.0;
   W* b0 = bufA;
   W* b1 = bufB;
   N::begin(wg, b0);
@@ -561,9 +575,36 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
     Pk<MTH> hp[NH];
-    N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
     bf16x8 bo[KBO];
-    DOut<K, 1>::load_operands(a.dout, tile * kBwdWaves + wave, bo, lane);
+    if constexpr (GROUP == 1) {
+      float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f;
+      if (valid) {
+        vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
+        wj = a.w[v];
+      }
+      N::hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), N::HALF_O * 16 * H, lane);   // output half 0 -> b0
+      float out[MTO][4];
+      N::output(wg, b0, b1, hp[NH - 1], out, out_bwd, N::OB_HALF, lane);          // output-dgrad half 0 -> b0
+      const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+      vx *= inv; vy *= inv; vz *= inv;
+      const float gs = valid ? -wj * inv_b : 0.0f;
+      float dl[MTO][4];
+      const float logq = train_epilogue<N::KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl);
+      if (valid && g == 0) {
+        loss_sum += (double)wj * (double)(-logq);
+        w_sum += (double)wj;
+      }
+#pragma unroll
+      for (int kb = 0; kb < KBO; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bo[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
+      bf16x8* d = reinterpret_cast<bf16x8*>(a.dout) + (tile * kBwdWaves + wave) * KBO * 64 + lane;
+#pragma unroll
+      for (int kb = 0; kb < KBO; ++kb) d[kb * 64] = bo[kb];
+    } else {
+      N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
+      DOut<K, 1>::load_operands(a.dout, tile * kBwdWaves + wave, bo, lane);
+    }
     float dh[MTH][4];
     Pk<MTH> dhw;
     if constexpr (GROUP == 0) {
@@ -645,6 +686,22 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
 #pragma unroll
     for (int l = 1; l <= NH - 2; ++l) flush_tiles<1, CTH>(part, dims, l, rt, 1, accM[l - 1], lane);
     flush_tiles<1, 1>(part, dims, 0, rt, 1, acc0, lane);
+    // loss partials: wave reduction, then the waves in order
+    __shared__ double red[kBwdWaves][2];
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+      loss_sum += __shfl_xor(loss_sum, s);
+      w_sum += __shfl_xor(w_sum, s);
+    }
+    if (lane == 0) { red[wave][0] = loss_sum; red[wave][1] = w_sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ls = 0.0, ws = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBwdWaves; ++w) { ls += red[w][0]; ws += red[w][1]; }
+      a.loss_partial[2 * blockIdx.x] = ls;
+      a.loss_partial[2 * blockIdx.x + 1] = ws;
+    }
   }
 }
 
@@ -797,8 +854,9 @@ static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t
   return hipGetLastError();
 }
 
-int gradout_workgroups(int64_t B, int num_cus) {
-  const int64_t t = (B + kWGV - 1) / kWGV;
+int large_loss_workgroups(int64_t B, int num_cus, int prec) {
+  if (prec == 1) return train_workgroups(B, num_cus);   // the fused backward kernel's grid
+  const int64_t t = (B + kWGV - 1) / kWGV;               // the FP32 gradient kernel: two per CU
   const int64_t cap = 2LL * (num_cus < kMaxTrainWG ? num_cus : kMaxTrainWG);
   return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
 }
@@ -812,16 +870,22 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
   auto k_bwd1 = PREC == 1 ? bwd_bf16_kernel<H, K, 1> : bwd_f32_kernel<H, K, 1>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = set_lds(k_grad, sh_fwd);
+    hipError_t e = PREC == 1 ? hipSuccess : set_lds(k_grad, sh_fwd);
     if (e == hipSuccess) e = set_lds(k_bwd0, sh_bwd);
     if (e == hipSuccess) e = set_lds(k_bwd1, sh_bwd);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), sh_fwd, st, a);
   const int bt = LargeLds<H, K, PREC>::bwd_threads;
-  hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
-  hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+  if (PREC == 1) {
+    // the group-1 kernel computes and stores the raw-output gradient first
+    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+  } else {
+    hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), sh_fwd, st, a);
+    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+  }
   return hipGetLastError();
 }
 
