@@ -22,7 +22,11 @@ Readings of the paper where it is silent (each repeated where it is used):
 * raw output order is parameter-major, lobe-minor: for lobe k and parameter p
   the raw value is ``o[p*K + k]`` with p = 0..7 meaning
   (cos theta, sin phi, cos phi, sin tau, cos tau, log lambda, log a, logit);
-  the selection probability c of Sec. 4.2 is not part of this output;
+  a network with the selection probability c of Sec. 4.2 has one more
+  output, ``o[8K]``, decoded as sigmoid;
+* the blended loss of Sec. 4.2 uses q_hat = c q + (1 - c) p_fs with the
+  BSDF pdf p_fs supplied per sample; the blend ramp b of Sec. 5 rises by
+  1/B after every M images (M = 4, B = 64), capped at 1;
 * sin theta = sqrt(1 - cos^2 theta); the (cos, sin) pairs of phi and tau are
   divided by their norm so the frame is exactly orthonormal (a zero pair maps
   to (1, 0)); y = z x x;

@@ -15,11 +15,13 @@ F64 = torch.float64
 IN_FEATURES = 9
 
 
-def layer_shapes(hidden, n_hidden, n_lobes):
-    """[(out, in)] for n_hidden hidden layers of width `hidden` and 8K outputs."""
+def layer_shapes(hidden, n_hidden, n_lobes, selection=False):
+    """[(out, in)] for n_hidden hidden layers of width `hidden` and 8K outputs,
+    plus one for the selection probability (Sec. 4.1: d = 8N + 1) when
+    `selection` is set."""
     shapes = [(hidden, IN_FEATURES + 1)]
     shapes += [(hidden, hidden)] * (n_hidden - 1)
-    shapes.append((8 * n_lobes, hidden))
+    shapes.append((8 * n_lobes + (1 if selection else 0), hidden))
     return shapes
 
 

@@ -77,14 +77,16 @@ def euler_frame(ct, st, cp, sp, ctau, stau):
 
 
 def decode(raw, n_lobes, eps=0.0):
-    """Raw network outputs [B, 8K] -> Lobes (Tab. "decoding", Sec. 4.1).
+    """Raw network outputs [B, 8K] (or [B, 8K + 1]) -> Lobes (Tab. "decoding",
+    Sec. 4.1).
 
-    Raw order (reading): o[:, p*K + k] is parameter p of lobe k.
+    Raw order (reading): o[:, p*K + k] is parameter p of lobe k; a column
+    8K, when present, is the selection probability (see ``selection``).
     cos/sin values: sigmoid(s0) * 2 - 1; lambda, a: exp(s1) (after the clamp);
     mixture weights: softmax over the K logits.
     """
     raw = torch.as_tensor(raw, dtype=F64)
-    r = raw.reshape(raw.shape[0], N_PARAM, n_lobes)
+    r = raw[:, :N_PARAM * n_lobes].reshape(raw.shape[0], N_PARAM, n_lobes)
     d = torch.sigmoid(r[:, 0:5, :]) * 2.0 - 1.0
     ct = d[:, 0]
     st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
@@ -96,6 +98,12 @@ def decode(raw, n_lobes, eps=0.0):
     log_A = torch.log_softmax(r[:, 7], dim=-1)
     return Lobes(z=z, x=x, y=y, lam=lam, a=a, log_A=log_A,
                  log_K=log_normaliser(lam, a, eps), eps=float(eps))
+
+
+def selection(raw, n_lobes):
+    """Selection probability c = sigmoid(o[8K]) (Tab. "decoding"), [B]."""
+    raw = torch.as_tensor(raw, dtype=F64)
+    return torch.sigmoid(raw[:, N_PARAM * n_lobes])
 
 
 def lobes_from_record(rec, eps=0.0):

@@ -458,3 +458,108 @@ def test_weight_grad_from_raw_grad_is_the_chain_rule():
     staged = train.weight_grad_from_raw_grad(Ws, feat, g_raw)
     for a, b in zip(full, staged):
         assert torch.allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+# ---- selection probability and the blended loss (Sec. 4.2, Sec. 5) ----
+
+def _tiny_selection_net(rng, K=2, hidden=8, n_hidden=2):
+    return [torch.tensor(rng.uniform(-0.6, 0.6, s)) for s in mlp.layer_shapes(hidden, n_hidden, K, selection=True)]
+
+
+def _batch(rng, B):
+    feat = torch.tensor(rng.standard_normal((B, 9)))
+    d = rng.standard_normal((B, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return feat, torch.tensor(d), torch.tensor(np.exp(rng.standard_normal(B)))
+
+
+def test_selection_output_shape_and_decoding():
+    """d = 8N + 1 outputs (Sec. 4.1); the last decodes as sigmoid (Tab.
+    "decoding"): a constant logit of 0 gives c = 1/2, of log 3 gives 3/4."""
+    assert mlp.layer_shapes(64, 4, 16, selection=True)[-1] == (129, 64)
+    for logit, c in ((0.0, 0.5), (math.log(3.0), 0.75)):
+        raw = np.concatenate([np.zeros(8), [logit]])
+        Ws = _constant_output_net(raw)
+        out = mlp.forward(Ws, torch.zeros(3, 9))
+        assert torch.allclose(nasg.selection(out, 1), torch.full((3,), c, dtype=F64), rtol=0, atol=1e-15)
+
+
+def test_blended_loss_limits():
+    """e = 0 leaves KL(p || q) alone: the blended loss equals the weighted NLL
+    and the selection row receives no gradient. With p_fs equal to q at each
+    training direction, q_hat = q for every c: again the weighted NLL for any
+    e, a zero selection gradient (to rounding), and for the lobe outputs
+    d log q_hat = c d log q, so their raw-output gradient is the NLL's scaled
+    per sample by e c + (1 - e)."""
+    rng = np.random.default_rng(31)
+    K = 2
+    Ws = _tiny_selection_net(rng, K)
+    feat, dirs, w = _batch(rng, 40)
+    pdf = torch.tensor(np.exp(rng.uniform(-2, 1, 40)))
+    nll = float(train.weighted_nll(Ws, feat, dirs, w, K))
+    L0, g0 = train.blended_loss_and_grad(Ws, feat, dirs, w, pdf, K, e=0.0)
+    assert abs(L0 - nll) < 1e-12 * abs(nll)
+    assert float(torch.abs(g0[-1][-1]).max()) == 0.0
+    q = torch.exp(nasg.mixture_log_pdf(dirs, nasg.decode(mlp.forward(Ws, feat), K)))
+    Lq, gq = train.blended_loss_and_grad(Ws, feat, dirs, w, q, K, e=0.7)
+    assert abs(Lq - nll) < 1e-12 * abs(nll)
+    assert float(torch.abs(gq[-1][-1]).max()) < 1e-13
+    raw = mlp.forward(Ws, feat)
+    gb = train.blended_raw_output_grad(raw, dirs, w, q, K, e=0.7)
+    gn = train.raw_output_grad(raw[:, :8 * K], dirs, w, K)
+    c = nasg.selection(raw, K)
+    assert torch.allclose(gb[:, :8 * K], gn * (0.7 * c + 0.3)[:, None], rtol=1e-10, atol=1e-15)
+    assert float(torch.abs(gb[:, 8 * K]).max()) < 1e-15
+
+
+def test_blended_loss_value_by_hand():
+    """One lobe of eccentricity exp(-15) is the vMF density to ~1e-7 (scipy),
+    c = sigmoid(0.4), p_fs given: the loss is mean w -(e log(c q + (1-c) p)
+    + (1-e) log q) computed from scipy's vMF, not from the oracle's mixture."""
+    rng = np.random.default_rng(32)
+    lam, logit, e = 5.0, 0.4, 0.2
+    raw = np.array([0.7, -0.3, 1.1, 0.4, -0.8, math.log(lam), -15.0, 0.0, logit])
+    Ws = _constant_output_net(raw)
+    feat, dirs, w = _batch(rng, 64)
+    pdf = np.exp(rng.uniform(-3, 0.5, 64))
+    z = nasg.decode(torch.tensor(raw[None]), 1).z[0, 0].numpy()
+    q = np.exp(ss.vonmises_fisher(mu=z, kappa=lam).logpdf(dirs.numpy()))
+    c = 1.0 / (1.0 + math.exp(-logit))
+    ref = np.mean(w.numpy() * -(e * np.log(c * q + (1 - c) * pdf) + (1 - e) * np.log(q)))
+    L = float(train.blended_nll(Ws, feat, dirs, w, torch.tensor(pdf), 1, e=e))
+    assert abs(L - ref) < 1e-5 * abs(ref)
+
+
+def test_blended_gradient_matches_finite_differences():
+    """The blended loss's autograd gradient against central differences, every
+    weight of a tiny network with the selection output."""
+    rng = np.random.default_rng(33)
+    K = 2
+    Ws = _tiny_selection_net(rng, K)
+    feat, dirs, w = _batch(rng, 6)
+    pdf = torch.tensor(np.exp(rng.uniform(-2, 1, 6)))
+    L, g = train.blended_loss_and_grad(Ws, feat, dirs, w, pdf, K, e=0.2)
+    for l, W in enumerate(Ws):
+        flat = W.reshape(-1)
+        fd = torch.zeros_like(flat)
+        for i in range(flat.numel()):
+            h = 1e-6 * max(1.0, abs(float(flat[i])))
+            wp = [x.clone() for x in Ws]; wp[l].view(-1)[i] += h
+            wm = [x.clone() for x in Ws]; wm[l].view(-1)[i] -= h
+            fd[i] = (train.blended_nll(wp, feat, dirs, w, pdf, K, 0.2)
+                     - train.blended_nll(wm, feat, dirs, w, pdf, K, 0.2)) / (2 * h)
+        err = torch.abs(fd - g[l].reshape(-1))
+        assert float(err.max()) < 1e-6 * max(1.0, float(torch.abs(g[l]).max())), l
+    # the raw-output form composes to the same weight gradient
+    g_raw = train.blended_raw_output_grad(mlp.forward(Ws, feat), dirs, w, pdf, K, e=0.2)
+    for a, b in zip(train.weight_grad_from_raw_grad(Ws, feat, g_raw), g):
+        assert torch.allclose(a, b, rtol=1e-11, atol=1e-14)
+
+
+def test_blend_ramp_schedule():
+    """Sec. 5: b starts at 0 and rises by 1/B after every M images (M = 4,
+    B = 64), reaching 1 after M B = 256 images."""
+    assert train.blend_ramp(0) == 0.0 and train.blend_ramp(3) == 0.0
+    assert train.blend_ramp(4) == 1 / 64 and train.blend_ramp(7) == 1 / 64
+    assert train.blend_ramp(255) == 63 / 64
+    assert train.blend_ramp(256) == 1.0 and train.blend_ramp(10 ** 6) == 1.0
+    assert train.blend_ramp(10, M=2, B=4) == 1.0 and train.blend_ramp(5, M=2, B=4) == 0.5
