@@ -49,8 +49,8 @@ enum { NASG_F32 = 0, NASG_BF16 = 1 };
 /* Network and optimiser configuration.
  * Layers: W_0 is [hidden][10] (9 features + the constant-one input that
  * stands in for the bias, footnote of Sec. 4.1), then n_hidden-1 matrices
- * [hidden][hidden], then the output W_L [8*n_lobes][hidden]. ReLU between
- * layers, none after the last (Sec. 4.1). */
+ * [hidden][hidden], then the output W_L [8*n_lobes + selection][hidden]. ReLU
+ * between layers, none after the last (Sec. 4.1). */
 typedef struct {
   int32_t hidden;      /* 64 or 128 */
   int32_t n_hidden;    /* number of hidden layers, 1..8 */
@@ -60,13 +60,19 @@ typedef struct {
   float eps;           /* NASG continuity parameter epsilon >= 0 (App. A); 0 = Sec. 3.2 */
   float lr, beta1, beta2, adam_eps;   /* Adam (Sec. 5; Kingma and Ba) */
   int64_t max_batch;   /* largest B accepted by training calls */
+  int32_t selection;   /* 1: one more output, the selection probability c = sigmoid(o[8K])
+                          (Sec. 4.1, Tab. "decoding"), and training on the blended loss
+                          e KL(p||q_hat) + (1-e) KL(p||q), q_hat = c q + (1-c) p_fs
+                          (Sec. 4.2); hidden-64 networks only. 0: 8K outputs, NLL of q. */
+  float mis_fraction;  /* e of the blended loss, in [0, 1] (the paper uses 0.2) */
 } nasg_config;
 
 /* Device state, allocated by the caller with the sizes given below.
  * Canonical weight layout: W_0, W_1, ..., W_L concatenated, each row-major
  * [out][in]. Raw output row order of W_L (reading; the paper does not fix it):
  * row p*K + k is parameter p of lobe k, p = 0..7 meaning cos theta, sin phi,
- * cos phi, sin tau, cos tau, log lambda, log a, mixture logit. */
+ * cos phi, sin tau, cos tau, log lambda, log a, mixture logit; with the
+ * selection output, row 8K is its logit. */
 typedef struct {
   float* w;            /* [nasg_num_weights] FP32 master weights (canonical)      */
   float* grad;         /* [nasg_num_weights] dL/dw written by nasg_loss_grad      */
@@ -75,7 +81,8 @@ typedef struct {
   void* wpack;         /* [nasg_packed_bytes] kernel-layout copy of w (16-B aligned) */
   int64_t* step;       /* [1] Adam updates taken so far                            */
   uint32_t* flags;     /* [1] bit 0: the last Adam step was skipped (non-finite)   */
-  double* stats;       /* [4] loss L, sum of w, gradient 2-norm, sum of w*(-log q) */
+  double* stats;       /* [4] loss L, sum of w, gradient 2-norm, sum of w*(-log term),
+                          the log term being log q, or e log q_hat + (1-e) log q */
   void* workspace;     /* [nasg_workspace_bytes] scratch (16-B aligned)            */
 } nasg_state;
 
@@ -95,7 +102,7 @@ const char* nasg_last_error(void);
 /* Re-pack state->w into state->wpack after the caller changed w directly. */
 nasg_status nasg_pack(nasg_ctx* ctx, void* stream);
 
-/* MLP forward only: raw outputs [8K][ld] in canonical row order (Sec. 4.1). */
+/* MLP forward only: raw outputs [8K + selection][ld] in canonical row order (Sec. 4.1). */
 nasg_status nasg_forward(nasg_ctx* ctx, const float* feat, int64_t ld, int64_t B,
                          float* raw_out, void* stream);
 
@@ -107,10 +114,14 @@ nasg_status nasg_forward(nasg_ctx* ctx, const float* feat, int64_t ld, int64_t B
  *                    eastern map of App. C
  *   dir_out [3][ld]  sampled unit direction
  *   pdf_out [B]      mixture pdf at dir_out, per steradian (Sec. 3.1)
+ *   sel_out [B]      optional (NULL = not written; requires selection = 1): the
+ *                    selection probability c. A renderer samples the learned
+ *                    distribution with probability b c (b from nasg_blend_ramp)
+ *                    and the BSDF otherwise; its MIS pdf is b c q + (1 - b c) p_fs.
  *   rec_out          optional (NULL = not written): decoded lobe records in the
  *                    layout described at nasg_pdf. */
 nasg_status nasg_query(nasg_ctx* ctx, const float* feat, const float* xi, int64_t ld, int64_t B,
-                       float* dir_out, float* pdf_out, float* rec_out, void* stream);
+                       float* dir_out, float* pdf_out, float* sel_out, float* rec_out, void* stream);
 
 /* Mixture pdf at caller directions from decoded records (Sec. 3.1, eq. NASG,
  * eq. "K for NASG"): the pdf a renderer needs for MIS against light samples.
@@ -127,12 +138,16 @@ nasg_status nasg_pdf(nasg_ctx* ctx, const float* rec, const float* dir, int64_t 
 nasg_status nasg_sample(nasg_ctx* ctx, const float* rec, const float* xi, int64_t ld, int64_t B,
                         float* dir_out, float* pdf_out, void* stream);
 
-/* Weighted NLL and its gradient (Sec. 4.2): L = (1/B) sum_j w_j (-log q(dir_j|feat_j)).
- *   feat [9][ld], dir [3][ld] (normalised inside), w [B] = p / q_hat per sample.
+/* Weighted NLL and its gradient (Sec. 4.2): L = (1/B) sum_j w_j (-log q(dir_j|feat_j)),
+ * or with selection = 1 the blended loss
+ * L = (1/B) sum_j w_j (-(e log q_hat_j + (1 - e) log q_j)), q_hat = c q + (1 - c) p_fs.
+ *   feat [9][ld], dir [3][ld] (normalised inside), w [B] = p / q_hat per sample
+ *   (q_hat: the density the sample was drawn from)
+ *   bsdf_pdf [B] p_fs at dir, required with selection = 1 and NULL otherwise.
  * Writes state->grad (canonical layout) and state->stats[0..1,3]. Activations
- * are recomputed, never stored. Requires B <= max_batch. */
+ * are recomputed, never stored. Requires 0 < B <= max_batch. */
 nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
-                           int64_t ld, int64_t B, void* stream);
+                           const float* bsdf_pdf, int64_t ld, int64_t B, void* stream);
 
 /* One Adam update of state->w from state->grad (bias-corrected, no decay), with
  * state->wpack refreshed in the same kernel. Skipped, with flags bit 0 set and
@@ -142,7 +157,12 @@ nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream);
 
 /* nasg_loss_grad followed by nasg_adam_step. */
 nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
-                            int64_t ld, int64_t B, void* stream);
+                            const float* bsdf_pdf, int64_t ld, int64_t B, void* stream);
+
+/* The blend ramp b of Sec. 5 (host only): 0 at the start, raised by 1/B after
+ * every M rendered images, capped at 1 (the paper uses M = 4, B = 64).
+ * Returns 0 for frames_done <= 0 or non-positive M, B. */
+float nasg_blend_ramp(int64_t frames_done, int32_t M, int32_t B);
 
 #ifdef __cplusplus
 }

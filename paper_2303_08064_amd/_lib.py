@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "NASG_OK", 1: "NASG_E_ARG", 2: "NASG_E_SHAPE", 3: "NASG_E_ALI
 EXPORTED = [
     "nasg_num_weights", "nasg_packed_bytes", "nasg_workspace_bytes", "nasg_create", "nasg_destroy",
     "nasg_last_error", "nasg_pack", "nasg_forward", "nasg_query", "nasg_pdf", "nasg_sample",
-    "nasg_loss_grad", "nasg_adam_step", "nasg_train_step",
+    "nasg_loss_grad", "nasg_adam_step", "nasg_train_step", "nasg_blend_ramp",
 ]
 
 
@@ -27,7 +27,7 @@ class Config(ctypes.Structure):
         ("hidden", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_lobes", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("eps", ctypes.c_float), ("lr", ctypes.c_float),
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
-        ("max_batch", ctypes.c_int64),
+        ("max_batch", ctypes.c_int64), ("selection", ctypes.c_int32), ("mis_fraction", ctypes.c_float),
     ]
 
 
@@ -69,12 +69,13 @@ def load():
         "nasg_last_error": (ctypes.c_char_p, []),
         "nasg_pack": (S, [P, P]),
         "nasg_forward": (S, [P, P, I64, I64, P, P]),
-        "nasg_query": (S, [P, P, P, I64, I64, P, P, P, P]),
+        "nasg_query": (S, [P, P, P, I64, I64, P, P, P, P, P]),
         "nasg_pdf": (S, [P, P, P, I64, I64, P, P]),
         "nasg_sample": (S, [P, P, P, I64, I64, P, P, P]),
-        "nasg_loss_grad": (S, [P, P, P, P, I64, I64, P]),
+        "nasg_loss_grad": (S, [P, P, P, P, P, I64, I64, P]),
         "nasg_adam_step": (S, [P, P]),
-        "nasg_train_step": (S, [P, P, P, P, I64, I64, P]),
+        "nasg_train_step": (S, [P, P, P, P, P, I64, I64, P]),
+        "nasg_blend_ramp": (ctypes.c_float, [I64, ctypes.c_int32, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

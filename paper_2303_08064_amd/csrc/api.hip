@@ -45,7 +45,7 @@ bool is_large(int H, int K, int prec) {
   return false;
 }
 
-NetDims dims_of(const nasg_config* c) { return NetDims{c->hidden, c->n_hidden, c->n_lobes}; }
+NetDims dims_of(const nasg_config* c) { return NetDims{c->hidden, c->n_hidden, c->n_lobes, c->selection}; }
 
 const char* config_error(const nasg_config* c) {
   if (c == nullptr) return "config is NULL";
@@ -56,6 +56,10 @@ const char* config_error(const nasg_config* c) {
            "n_lobes 32, each in FP32 or BF16";
   if (is_large(c->hidden, c->n_lobes, c->precision) && c->n_hidden != 4)
     return "hidden 128 networks are compiled for n_hidden = 4";
+  if (c->selection != 0 && c->selection != 1) return "selection must be 0 or 1";
+  if (c->selection == 1 && is_large(c->hidden, c->n_lobes, c->precision))
+    return "the selection output is compiled for hidden 64 networks";
+  if (!(c->mis_fraction >= 0.0f && c->mis_fraction <= 1.0f)) return "mis_fraction must be in [0, 1]";
   if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
   if (!(c->lr > 0.0f) || !isfinite(c->lr)) return "lr must be finite and > 0";
   if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
@@ -165,7 +169,8 @@ nasg_status nasg_create(const nasg_config* cfg, const nasg_state* st, nasg_ctx**
   c->d = dims_of(cfg);
   c->ws = carve(cfg);
   c->num_cus = cus > 0 ? cus : 1;
-  e = launch_pack(st->w, st->wpack, cfg->hidden, cfg->n_hidden, cfg->n_lobes, cfg->precision, nullptr);
+  e = launch_pack(st->w, st->wpack, cfg->hidden, cfg->n_hidden, cfg->n_lobes, cfg->selection, cfg->precision,
+                  nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     delete c;
@@ -179,8 +184,8 @@ void nasg_destroy(nasg_ctx* ctx) { delete ctx; }
 
 nasg_status nasg_pack(nasg_ctx* ctx, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_pack", "ctx is NULL");
-  hipError_t e = launch_pack(ctx->st.w, ctx->st.wpack, ctx->d.H, ctx->d.NH, ctx->d.K, ctx->cfg.precision,
-                             (hipStream_t)stream);
+  hipError_t e = launch_pack(ctx->st.w, ctx->st.wpack, ctx->d.H, ctx->d.NH, ctx->d.K, ctx->d.S,
+                             ctx->cfg.precision, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail("nasg_pack", e);
 }
 
@@ -203,8 +208,8 @@ static nasg_status check_ptr(const char* fn, const void* p, const char* name) {
   } while (0)
 
 static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, const float* xi, int64_t ld,
-                             int64_t B, float* dir_out, float* pdf_out, float* rec_out, float* raw_out, int mode,
-                             void* stream) {
+                             int64_t B, float* dir_out, float* pdf_out, float* sel_out, float* rec_out,
+                             float* raw_out, int mode, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
   NASG_TRY(check_batch(fn, ld, B));
   if (B == 0) return NASG_OK;
@@ -214,6 +219,10 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
     NASG_TRY(check_ptr(fn, dir_out, "dir_out"));
     NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
     if (rec_out != nullptr && !aligned(rec_out, 4)) return fail(NASG_E_ALIGN, fn, "rec_out is not 4-byte aligned");
+    if (sel_out != nullptr) {
+      if (ctx->cfg.selection != 1) return fail(NASG_E_ARG, fn, "sel_out needs a network with the selection output");
+      if (!aligned(sel_out, 4)) return fail(NASG_E_ALIGN, fn, "sel_out is not 4-byte aligned");
+    }
   } else {
     NASG_TRY(check_ptr(fn, raw_out, "raw_out"));
   }
@@ -230,6 +239,8 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.pdf_out = pdf_out;
   a.rec_out = rec_out;
   a.raw_out = raw_out;
+  a.sel_out = sel_out;
+  a.sel = ctx->d.S;
   a.num_cus = ctx->num_cus;
   hipError_t e = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)
                      ? launch_large_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream)
@@ -238,12 +249,13 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
 }
 
 nasg_status nasg_forward(nasg_ctx* ctx, const float* feat, int64_t ld, int64_t B, float* raw_out, void* stream) {
-  return run_query(ctx, "nasg_forward", feat, nullptr, ld, B, nullptr, nullptr, nullptr, raw_out, 1, stream);
+  return run_query(ctx, "nasg_forward", feat, nullptr, ld, B, nullptr, nullptr, nullptr, nullptr, raw_out, 1,
+                   stream);
 }
 
 nasg_status nasg_query(nasg_ctx* ctx, const float* feat, const float* xi, int64_t ld, int64_t B, float* dir_out,
-                       float* pdf_out, float* rec_out, void* stream) {
-  return run_query(ctx, "nasg_query", feat, xi, ld, B, dir_out, pdf_out, rec_out, nullptr, 0, stream);
+                       float* pdf_out, float* sel_out, float* rec_out, void* stream) {
+  return run_query(ctx, "nasg_query", feat, xi, ld, B, dir_out, pdf_out, sel_out, rec_out, nullptr, 0, stream);
 }
 
 nasg_status nasg_pdf(nasg_ctx* ctx, const float* rec, const float* dir, int64_t ld, int64_t B, float* pdf_out,
@@ -294,6 +306,7 @@ static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
   a.H = ctx->d.H;
   a.NH = ctx->d.NH;
   a.K = ctx->d.K;
+  a.S = ctx->d.S;
   a.prec = ctx->cfg.precision;
   a.lr = ctx->cfg.lr;
   a.beta1 = ctx->cfg.beta1;
@@ -303,8 +316,8 @@ static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
-nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w, int64_t ld,
-                           int64_t B, void* stream) {
+nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
+                           const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
   static const char* fn = "nasg_loss_grad";
   if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
   NASG_TRY(check_batch(fn, ld, B));
@@ -313,6 +326,8 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   NASG_TRY(check_ptr(fn, feat, "feat"));
   NASG_TRY(check_ptr(fn, dir, "dir"));
   NASG_TRY(check_ptr(fn, w, "w"));
+  if (ctx->cfg.selection == 1) NASG_TRY(check_ptr(fn, bsdf_pdf, "bsdf_pdf"));
+  else if (bsdf_pdf != nullptr) return fail(NASG_E_ARG, fn, "bsdf_pdf needs a network with the selection output");
   const nasg_state& s = ctx->st;
   unsigned char* ws = static_cast<unsigned char*>(s.workspace);
   const int n_wg = train_workgroups(B, ctx->num_cus);
@@ -332,6 +347,9 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   t.loss_partial = reinterpret_cast<double*>(ws + ctx->ws.loss_partial);
   t.n_weights = ctx->d.num_weights();
   t.num_cus = ctx->num_cus;
+  t.sel = ctx->d.S;
+  t.bsdf_pdf = bsdf_pdf;
+  t.mis_e = ctx->cfg.mis_fraction;
   hipError_t e;
   if (large) {
     LargeTrainArgs la;
@@ -372,10 +390,16 @@ nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream) {
   return adam_only(ctx, "nasg_adam_step", stream);
 }
 
-nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w, int64_t ld,
-                            int64_t B, void* stream) {
-  NASG_TRY(nasg_loss_grad(ctx, feat, dir, w, ld, B, stream));
+nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
+                            const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
+  NASG_TRY(nasg_loss_grad(ctx, feat, dir, w, bsdf_pdf, ld, B, stream));
   return adam_only(ctx, "nasg_train_step", stream);
+}
+
+float nasg_blend_ramp(int64_t frames_done, int32_t M, int32_t B) {
+  if (frames_done <= 0 || M <= 0 || B <= 0) return 0.0f;
+  const int64_t steps = frames_done / M;
+  return steps >= B ? 1.0f : (float)steps / (float)B;
 }
 
 }  // extern "C"

@@ -29,11 +29,28 @@ __device__ __forceinline__ void dgrad(const void* wl, const float (&dl)[RT][4],
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int j = 0; j < 8; ++j) b[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
+    // an odd last row tile (the selection tile) contracts with 16x16x16
+    // fragments stored after the 32-wide ones: lane (g, c) holds its rows
+    // 4g .. 4g+3, which are this lane's accumulators dl[RT-1][0..3]. Its
+    // product has an accumulator of its own, added with VALU: chaining a
+    // 16x16x16 MFMA onto a 16x16x32 accumulator gave non-reproducible
+    // results with this toolchain.
+    const bf16x4* frag_s = reinterpret_cast<const bf16x4*>(frag + MTP * KB * 64);
+    bf16x4 bs;
+    if constexpr (RT % 2 == 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[RT - 1][j];
+    }
 #pragma unroll
     for (int mt = 0; mt < MTP; ++mt) {
       f32x4 acc = zero4();
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+      if constexpr (RT % 2 == 1) {
+        const f32x4 sel = mfma_bf16_16(frag_s[mt * 64 + lane], bs, zero4());
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += sel[i];
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
     }
@@ -186,7 +203,7 @@ __device__ __forceinline__ void flush_own(float* part, const NetDims& d, int l,
     for (int i = 0; i < 4; ++i) {
       const int R = O::rt(wave, j) * 16 + 4 * g + i;
       const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-      part[off + (int64_t)n * cols + k] = acc[j][i];
+      if (n >= 0) part[off + (int64_t)n * cols + k] = acc[j][i];   // n < 0: padding rows
     }
   }
 }

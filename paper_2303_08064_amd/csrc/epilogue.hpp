@@ -41,17 +41,27 @@ __device__ __forceinline__ float logit_lse(const float (&out)[MTO][4]) {
 
 // Weighted NLL of one vertex and its gradient w.r.t. the raw outputs
 // (Sec. 4.2): gs = dL/dlog q = -w/B (0 for padding lanes). Writes dl in the
-// accumulator layout and returns log q.
+// accumulator layout and returns the vertex's log term (log q; with the
+// selection output, e log q_hat + (1 - e) log q).
 //
 // One pass over the lobes: each lobe is decoded and evaluated once, and its
 // log-density's partials d ell_k / d o_p (p < 7) go straight into dl. They
 // are linear in the upstream factor, which is only known once log q is:
-// dL/d o_p = gs r_k d ell_k / d o_p with r_k = q_k / q, and for the logit
-// dL/d o_7 = gs (r_k - A_k) (through the softmax). A second, cheap loop
+// dL/d o_p = gq r_k d ell_k / d o_p with r_k = q_k / q, and for the logit
+// dL/d o_7 = gq (r_k - A_k) (through the softmax). A second, cheap loop
 // scales them.
-template <int KQ, int MTO>
+//
+// S = 1 (selection output, the blended loss of Sec. 4.2): with c the
+// sigmoid of the selection logit (output row 8K, held by lane group 0) and
+// q_hat = c q + (1 - c) p_fs, the loss term e log q_hat + (1 - e) log q has
+// d/dlog q = e c q / q_hat + (1 - e), so gq = gs times that, and
+// d/dz (z the selection logit) = e (q - p_fs) c (1 - c) / q_hat.
+template <int KQ, int MTO, int S = 0>
 __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], float vx, float vy, float vz,
-                                                float gs, bool valid, float eps, float (&dl)[MTO][4]) {
+                                                float gs, bool valid, float eps, float (&dl)[MTO][4],
+                                                float pdf_bsdf = 0.0f, float mis_e = 0.0f) {
+  constexpr int TS = 2 * KQ;   // the selection tile (S = 1)
+  static_assert(MTO == 2 * KQ + S, "output tiles: 8K rows plus the selection tile");
   const float lse = logit_lse<KQ, MTO>(out);
   float ell[KQ];
 #pragma unroll
@@ -73,18 +83,33 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
     }
   }
   const float logq = mixture_lse<KQ>(ell);
+  float lterm = logq, gsq = gs;
+  if constexpr (S == 1) {
+    const int c = lane_id() & 15;
+    const float z = __shfl(out[TS][0], c);   // lane (0, c) holds row 8K of vertex c
+    const float cs = frcp(1.0f + fexp(-z));
+    const float qv = fexp(logq);
+    const float qh = fmaf(cs, qv - pdf_bsdf, pdf_bsdf);   // c q + (1 - c) p_fs
+    const float iqh = frcp(qh);
+    lterm = fmaf(mis_e, flog(qh), (1.0f - mis_e) * logq);
+    gsq = gs * fmaf(mis_e * cs, qv * iqh, 1.0f - mis_e);
+    const float gz = gs * mis_e * (qv - pdf_bsdf) * cs * (1.0f - cs) * iqh;
+    const bool g0 = lane_id() < 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dl[TS][i] = (g0 && i == 0) ? gz : 0.0f;
+  }
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     const int t7 = 7 * KQ + q;
     const float r = valid ? fexp(ell[q] - logq) : 0.0f;
     const float Aq = fexp(out[t7 >> 2][t7 & 3] - lse);
-    const float sc = gs * r;
+    const float sc = gsq * r;
 #pragma unroll
     for (int p = 0; p < 7; ++p) {
       const int t = p * KQ + q;
       dl[t >> 2][t & 3] *= sc;
     }
-    dl[t7 >> 2][t7 & 3] = gs * (r - Aq);
+    dl[t7 >> 2][t7 & 3] = gsq * (r - Aq);
   }
   // padding lanes (a branch taken only in a batch's last tile): zeroed
   // outright, so that no non-finite partial of their arbitrary lobes reaches
@@ -95,7 +120,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
 #pragma unroll
       for (int i = 0; i < 4; ++i) dl[mt][i] = 0.0f;
   }
-  return logq;
+  return lterm;
 }
 
 // Guiding query of one vertex: decode, inverse-CDF lobe choice, App. C

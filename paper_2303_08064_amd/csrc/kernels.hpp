@@ -28,6 +28,8 @@ struct QueryArgs {
   float* pdf_out;
   float* rec_out;
   float* raw_out;
+  float* sel_out;        // selection probability c per vertex (optional)
+  int sel;               // 1: the network has the selection output (8K + 1 rows)
   int num_cus;
 };
 
@@ -51,9 +53,12 @@ struct TrainArgs {
   const float* w;
   int64_t ld, B;
   float* partial;        // [n_wg][n_weights] dW partials, canonical layout
-  double* loss_partial;  // [n_wg][2]: sum w*(-log q), sum w
+  double* loss_partial;  // [n_wg][2]: sum w*(-log terms), sum w
   int64_t n_weights;
   int num_cus;
+  int sel;               // 1: selection output and the blended loss
+  const float* bsdf_pdf; // [B] p_fs at each training direction (sel = 1)
+  float mis_e;           // e of the blended loss (sel = 1)
 };
 
 struct LargeTrainArgs {
@@ -97,7 +102,7 @@ struct AdamArgs {
   const double* norm_partial;
   int n_norm;
   int64_t n_weights;
-  int H, NH, K, prec;
+  int H, NH, K, S, prec;
   float lr, beta1, beta2, adam_eps;
 };
 
@@ -173,7 +178,7 @@ hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, i
                               hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
-hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st);
+hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int S, int prec, hipStream_t st);
 hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st);
 
 // Query / train kernel grid bounds (workgroups) for a batch of B vertices.

@@ -41,16 +41,20 @@ NASG_HD int inv_phys_f32(int n) {
   return (a * 4 + i) * 4 + g;
 }
 
-// canonical output row (p*K + k) held at physical output row R
+// canonical output row (p*K + k) held at physical output row R; rows from
+// 8K form one more 16-row tile when the network has the selection output:
+// its row 8K is canonical row 8K, the rest padding (-1)
 NASG_HD int canon_out_row(int R, int K) {
+  if (R >= 8 * K) return R == 8 * K ? 8 * K : -1;
   int mt = R >> 4, g = (R & 15) >> 2, i = R & 3;
   int t = mt * 4 + i;
   int kq = K / 4;
   return (t / kq) * K + g * kq + (t % kq);
 }
 
-// physical output row holding canonical row n = p*K + k
+// physical output row holding canonical row n = p*K + k (or the selection row 8K)
 NASG_HD int inv_canon_out_row(int n, int K) {
+  if (n >= 8 * K) return n;
   int kq = K / 4;
   int p = n / K, k = n % K;
   int g = k / kq, q = k % kq;
@@ -60,32 +64,36 @@ NASG_HD int inv_canon_out_row(int n, int K) {
 
 struct NetDims {
   int H, NH, K;
-  NASG_HD int nout() const { return 8 * K; }
+  int S = 0;   // 1: one more output, the selection probability (8K + 1 outputs)
+  NASG_HD int nout() const { return 8 * K + S; }
+  NASG_HD int out_rows() const { return 8 * K + 16 * S; }   // physical, padded to whole tiles
   NASG_HD int layers() const { return NH + 1; }
-  NASG_HD int rows(int l) const { return l == NH ? 8 * K : H; }
+  NASG_HD int rows(int l) const { return l == NH ? 8 * K + S : H; }
   NASG_HD int cols(int l) const { return l == 0 ? kInFeatures + 1 : H; }
   // canonical flat offset of W_l
   NASG_HD int64_t canon_off(int l) const {
     if (l == 0) return 0;
     return (int64_t)H * (kInFeatures + 1) + (int64_t)(l - 1) * H * H;
   }
-  NASG_HD int64_t num_weights() const { return canon_off(NH) + (int64_t)8 * K * H; }
+  NASG_HD int64_t num_weights() const { return canon_off(NH) + (int64_t)(8 * K + S) * H; }
 };
 
 // ---- BF16 fragment layout (elements are bf16) ----
-// forward: L0 [H/16][64][4]; hidden l [H/16][H/32][64][8]; out [K/2][H/32][64][8]
-// backward (W^T): hidden l [H/16][H/32][64][8]; out [H/16][8K/32][64][8]
+// forward: L0 [H/16][64][4]; hidden l [H/16][H/32][64][8]; out [K/2 (+1)][H/32][64][8]
+// backward (W^T): hidden l [H/16][H/32][64][8]; out [H/16][8K/32][64][8], then
+// for the selection tile the 16x16x16 A operands [H/16][64][4]
 struct Bf16Layout {
   NetDims d;
   NASG_HD int64_t fwd_off(int l) const {
     if (l == 0) return 0;
     return (int64_t)d.H * 16 + (int64_t)(l - 1) * d.H * d.H;
   }
-  NASG_HD int64_t fwd_elems() const { return fwd_off(d.NH) + (int64_t)8 * d.K * d.H; }
+  NASG_HD int64_t fwd_elems() const { return fwd_off(d.NH) + (int64_t)d.out_rows() * d.H; }
   NASG_HD int64_t bwd_off(int l) const {   // l >= 1
     return fwd_elems() + (int64_t)(l - 1) * d.H * d.H;
   }
-  NASG_HD int64_t total_elems() const { return bwd_off(d.NH) + (int64_t)8 * d.K * d.H; }
+  NASG_HD int64_t bwd_sel_off() const { return bwd_off(d.NH) + (int64_t)8 * d.K * d.H; }
+  NASG_HD int64_t total_elems() const { return bwd_sel_off() + (int64_t)16 * d.S * d.H; }
 };
 
 // ---- FP32 row-major layout (elements are float) ----
@@ -97,7 +105,7 @@ struct F32Layout {
     if (l == 0) return 0;
     return (int64_t)d.H * pitch(0) + (int64_t)(l - 1) * d.H * pitch(1);
   }
-  NASG_HD int64_t total_elems() const { return off(d.NH) + (int64_t)8 * d.K * pitch(d.NH); }
+  NASG_HD int64_t total_elems() const { return off(d.NH) + (int64_t)d.out_rows() * pitch(d.NH); }
 };
 
 }  // namespace nasg
@@ -122,6 +130,10 @@ NASG_HD int64_t bf16_fwd_pos(const Bf16Layout& Lt, int l, int n, int k) {
 NASG_HD int64_t bf16_bwd_pos(const Bf16Layout& Lt, int l, int n, int k) {
   const NetDims& d = Lt.d;
   int R = (l == d.NH) ? inv_canon_out_row(n, d.K) : n;
+  if (l == d.NH && R >= 8 * d.K) {   // selection tile: lane (g, c) holds rows 4g..4g+3, column c
+    const int r = R - 8 * d.K, mt = k >> 4, c = k & 15;
+    return Lt.bwd_sel_off() + ((int64_t)(mt * 64 + (r >> 2) * 16 + c) * 4 + (r & 3));
+  }
   int kl = inv_phys_bf16(R);
   int KB = (l == d.NH) ? (8 * d.K) / 32 : d.H / 32;
   int mt = k >> 4, c = k & 15, kb = kl >> 5, g = (kl & 31) >> 3, j = kl & 7;
@@ -153,7 +165,15 @@ NASG_HD void bf16_source(const Bf16Layout& Lt, int64_t e, int& l, int& n, int& k
     int kb = (int)((el >> 9) % KB), mt = (int)((el >> 9) / KB);
     int R = mt * 16 + (lane & 15);
     n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-    k = phys_bf16(kb * 32 + 8 * (lane >> 4) + j);
+    k = n < 0 ? -1 : phys_bf16(kb * 32 + 8 * (lane >> 4) + j);
+    return;
+  }
+  if (e >= Lt.bwd_sel_off()) {
+    l = d.NH;
+    const int64_t el = e - Lt.bwd_sel_off();
+    const int j = (int)(el & 3), lane = (int)((el >> 2) & 63), mt = (int)(el >> 8);
+    n = canon_out_row(8 * d.K + 4 * (lane >> 4) + j, d.K);
+    k = n < 0 ? -1 : mt * 16 + (lane & 15);
     return;
   }
   l = 1 + (int)((e - Lt.bwd_off(1)) / ((int64_t)d.H * d.H));
@@ -179,7 +199,7 @@ NASG_HD void f32_source(const F32Layout& Lt, int64_t e, int& l, int& n, int& k) 
   int R = (int)(el / Lt.pitch(l));
   k = (int)(el % Lt.pitch(l));
   n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-  if (k >= d.cols(l)) k = -1;
+  if (k >= d.cols(l) || n < 0) k = -1;
 }
 
 }  // namespace nasg

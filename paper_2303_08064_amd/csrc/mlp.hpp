@@ -181,18 +181,21 @@ struct Mlp<H, K, 0> {
 };
 
 // Forward through all layers; h[l] keeps hidden activations for the backward.
-template <int H, int K, int PREC, int NHMAX>
+// S = 1: the output layer has one more 16-row tile whose row 0 is the
+// selection logit (rows 8K .. 8K+15; the rest are zero padding).
+template <int H, int K, int PREC, int NHMAX, int S = 0>
 struct Forward {
   typedef Mlp<H, K, PREC> M;
   typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
+  static constexpr int MTO = M::MTO + S;   // output row tiles
 
   // offsets (elements) of each layer's forward weights in LDS
   __device__ static const W* layer_ptr(const W* lds, int l, int nh) {
     if (PREC == 1) {
-      Bf16Layout Lt{NetDims{H, nh, K}};
+      Bf16Layout Lt{NetDims{H, nh, K, S}};
       return lds + Lt.fwd_off(l);
     } else {
-      F32Layout Lt{NetDims{H, nh, K}};
+      F32Layout Lt{NetDims{H, nh, K, S}};
       return lds + Lt.off(l);
     }
   }
@@ -202,7 +205,7 @@ struct Forward {
   // branches; no array is indexed by a runtime value.
   __device__ static void run(const W* lds, int nh, const typename M::Input& x,
                              float (&h)[NHMAX][M::MTH][4], float (&last)[M::MTH][4],
-                             float (&out)[M::MTO][4], int lane) {
+                             float (&out)[MTO][4], int lane) {
     M::layer0(layer_ptr(lds, 0, nh), x, h[0], lane);
 #pragma unroll
     for (int mt = 0; mt < M::MTH; ++mt)
@@ -222,12 +225,12 @@ struct Forward {
           }
       }
     }
-    M::template gemm<M::MTO>(layer_ptr(lds, nh, nh), last, out, lane);
+    M::template gemm<MTO>(layer_ptr(lds, nh, nh), last, out, lane);
   }
 
   // Forward for queries (no activations kept): in BF16 the layers pass
   // packed, ReLU'd B operands; the same values as run().
-  __device__ static void run_query(const W* lds, int nh, const typename M::Input& x, float (&out)[M::MTO][4],
+  __device__ static void run_query(const W* lds, int nh, const typename M::Input& x, float (&out)[MTO][4],
                                    int lane) {
     if constexpr (PREC == 1) {
       float y[M::MTH][4];
@@ -241,7 +244,7 @@ struct Forward {
           M::relu_operands(y, b);
         }
       }
-      M::template gemm_op<M::MTO>(layer_ptr(lds, nh, nh), b, out, lane);
+      M::template gemm_op<MTO>(layer_ptr(lds, nh, nh), b, out, lane);
     } else {
       float h[NHMAX][M::MTH][4];
       float last[M::MTH][4];

@@ -13,12 +13,14 @@
 
 namespace nasg {
 
-template <int H, int K, int PREC, int MODE>   // MODE 0: query, 1: raw forward only
+// MODE 0: query, 1: raw forward only; S = 1: the network has the selection
+// output (row 8K, read by lane group 0 from the extra output tile)
+template <int H, int K, int PREC, int MODE, int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 3 : 1))) void query_kernel(QueryArgs a) {
   constexpr int NHMAX = 4;
   constexpr int KQ = K / 4;
   typedef Mlp<H, K, PREC> M;
-  typedef Forward<H, K, PREC, NHMAX> F;
+  typedef Forward<H, K, PREC, NHMAX, S> F;
   typedef typename F::W W;
   extern __shared__ __align__(16) unsigned char smem[];
   W* lds = reinterpret_cast<W*>(smem);
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
     const int64_t v = tile * kTileV + c;
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    float out[M::MTO][4];
+    float out[F::MTO][4];
     F::run_query(wts, a.nh, x, out, lane);
 
     if (MODE == 1) {
@@ -46,6 +48,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
           int p = t / KQ, k = g * KQ + t % KQ;
           a.raw_out[(int64_t)(p * K + k) * a.ld + v] = out[t >> 2][t & 3];
         }
+        if (S == 1 && g == 0) a.raw_out[(int64_t)(8 * K) * a.ld + v] = out[F::MTO - 1][0];
       }
       continue;
     }
@@ -59,13 +62,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
     }
     Lobe lb[KQ];
     float vx, vy, vz;
-    const float logq = query_epilogue<KQ, M::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz);
+    const float logq = query_epilogue<KQ, F::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz);
 
     if (valid && g == 0) {
       a.dir_out[v] = vx;
       a.dir_out[a.ld + v] = vy;
       a.dir_out[2 * a.ld + v] = vz;
       a.pdf_out[v] = fexp(logq);
+      // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
+      if (S == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[F::MTO - 1][0]));
     }
     if (a.rec_out != nullptr && valid) {
       float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
@@ -81,9 +86,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
   }
 }
 
-template <int H, int K, int PREC>
-static hipError_t launch_query_t(const QueryArgs& a, int mode, hipStream_t st) {
-  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0> : query_kernel<H, K, PREC, 1>;
+template <int H, int K, int PREC, int S>
+static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
+  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S> : query_kernel<H, K, PREC, 1, S>;
   // occupancy depends on the LDS footprint; cache it per (mode, footprint)
   static int cached_bytes[2] = {-1, -1};
   static int cached_per_cu[2] = {1, 1};
@@ -103,6 +108,11 @@ static hipError_t launch_query_t(const QueryArgs& a, int mode, hipStream_t st) {
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), a.lds_bytes, st, a);
   return hipGetLastError();
+}
+
+template <int H, int K, int PREC>
+static hipError_t launch_query_t(const QueryArgs& a, int mode, hipStream_t st) {
+  return a.sel ? launch_query_s<H, K, PREC, 1>(a, mode, st) : launch_query_s<H, K, PREC, 0>(a, mode, st);
 }
 
 hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st) {

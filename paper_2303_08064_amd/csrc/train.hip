@@ -24,19 +24,20 @@ namespace nasg {
 template <int PREC>
 constexpr int train_waves() { return PREC == 1 ? 8 : 4; }
 
-template <int H, int K, int PREC>
+template <int H, int K, int PREC, int SEL>
 struct TrainCfg {
   typedef Mlp<H, K, PREC> M;
   typedef typename std::conditional<PREC == 1, __bf16, float>::type S;   // staging type
   static constexpr int NHMAX = 4;
   static constexpr int KQ = K / 4;
-  static constexpr int MTH = H / 16, MTO = K / 2;
+  static constexpr int MTH = H / 16;
+  static constexpr int MTO = K / 2 + SEL;       // output row tiles (+ the selection tile)
   static constexpr int CTH = H / 16;            // column tiles of dW (hidden input)
   // BF16: eight waves (two per SIMD) over 128-vertex tiles; FP32 (larger
   // weights and staging): four waves over 64-vertex tiles
   static constexpr int NW = train_waves<PREC>();
   static constexpr int NV = 16 * NW;            // vertices per tile
-  static constexpr int RMAX = (8 * K > H) ? 8 * K : H;   // rows of the largest delta
+  static constexpr int RMAX = (16 * MTO > H) ? 16 * MTO : H;   // rows of the largest delta
   static constexpr int SP = PREC == 1 ? NV + 8 : NV + 4;   // staging pitch (elements)
   typedef Own<MTH, 1, NW> O0;                   // layer 0
   typedef Own<MTH, CTH, NW> OH;                 // hidden layers
@@ -45,27 +46,29 @@ struct TrainCfg {
 };
 
 // weights of layer l in LDS (forward and, for l >= 1, backward)
-template <int H, int K, int PREC>
+template <int H, int K, int PREC, int SEL>
 struct TrainLds {
   typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
   __device__ static const W* fwd(const W* lds, int l, int nh) {
-    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K}}.fwd_off(l);
-    return lds + F32Layout{NetDims{H, nh, K}}.off(l);
+    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K, SEL}}.fwd_off(l);
+    return lds + F32Layout{NetDims{H, nh, K, SEL}}.off(l);
   }
   __device__ static const W* bwd(const W* lds, int l, int nh) {
-    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K}}.bwd_off(l);
-    return lds + F32Layout{NetDims{H, nh, K}}.off(l);
+    if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K, SEL}}.bwd_off(l);
+    return lds + F32Layout{NetDims{H, nh, K, SEL}}.off(l);
   }
 };
 
-template <int H, int K, int PREC>
+// SEL = 1: the network has the selection output and the loss is the blend
+// of Sec. 4.2 (the BSDF pdf at each training direction is an input)
+template <int H, int K, int PREC, int SEL>
 __global__ __launch_bounds__(64 * train_waves<PREC>())
 __attribute__((amdgpu_waves_per_eu(train_waves<PREC>() / 4, train_waves<PREC>() / 4)))
 void train_kernel(TrainArgs a) {
-  typedef TrainCfg<H, K, PREC> C;
+  typedef TrainCfg<H, K, PREC, SEL> C;
   typedef typename C::M M;
   typedef typename C::S S;
-  typedef TrainLds<H, K, PREC> TL;
+  typedef TrainLds<H, K, PREC, SEL> TL;
   typedef typename TL::W W;
   constexpr int NHMAX = C::NHMAX, KQ = C::KQ, MTH = C::MTH, MTO = C::MTO, SP = C::SP, NW = C::NW, NV = C::NV;
   constexpr int CTH = C::CTH;
@@ -81,7 +84,7 @@ void train_kernel(TrainArgs a) {
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
   const int nh = a.nh;
-  const NetDims dims{H, nh, K};
+  const NetDims dims{H, nh, K, SEL};
   const float inv_b = 1.0f / (float)a.B;
 
   f32x4 acc0[C::O0::TPW];
@@ -106,21 +109,22 @@ void train_kernel(TrainArgs a) {
     float h[NHMAX][MTH][4];
     float last[MTH][4];
     float out[MTO][4];
-    Forward<H, K, PREC, NHMAX>::run(lds, nh, x, h, last, out, lane);
+    Forward<H, K, PREC, NHMAX, SEL>::run(lds, nh, x, h, last, out, lane);
 
     // ---- weighted NLL and its gradient w.r.t. the raw outputs ----
-    float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f;
+    float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f, pfs = 0.0f;
     if (valid) {
       vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
       wj = a.w[v];
+      if (SEL == 1) pfs = a.bsdf_pdf[v];
       float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
     }
-    const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q
+    const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q (of the log term)
     float dl[MTO][4];
-    const float logq = train_epilogue<KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl);
+    const float lterm = train_epilogue<KQ, MTO, SEL>(out, vx, vy, vz, gs, valid, a.eps, dl, pfs, a.mis_e);
     if (valid && g == 0) {
-      loss_sum += (double)wj * (double)(-logq);
+      loss_sum += (double)wj * (double)(-lterm);
       w_sum += (double)wj;
     }
 
@@ -215,16 +219,16 @@ int train_workgroups(int64_t B, int num_cus) {
   return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
 }
 
-template <int H, int K, int PREC>
-static hipError_t launch_train_t(const TrainArgs& a, int n_wg, hipStream_t st) {
-  typedef TrainCfg<H, K, PREC> C;
+template <int H, int K, int PREC, int SEL>
+static hipError_t launch_train_s(const TrainArgs& a, int n_wg, hipStream_t st) {
+  typedef TrainCfg<H, K, PREC, SEL> C;
   const size_t stage = sizeof(typename C::S) * C::stage_elems();
   const size_t shmem = (size_t)a.lds_bytes + stage;
-  auto kern = train_kernel<H, K, PREC>;
+  auto kern = train_kernel<H, K, PREC, SEL>;
   static bool attr_set = false;
   if (!attr_set) {
     // the largest footprint of this network shape (4 hidden layers)
-    const NetDims d{H, C::NHMAX, K};
+    const NetDims d{H, C::NHMAX, K, SEL};
     const size_t wmax = PREC == 1 ? (size_t)Bf16Layout{d}.total_elems() * 2 : (size_t)F32Layout{d}.total_elems() * 4;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(wmax + stage));
@@ -233,6 +237,11 @@ static hipError_t launch_train_t(const TrainArgs& a, int n_wg, hipStream_t st) {
   }
   hipLaunchKernelGGL(kern, dim3(n_wg), dim3(64 * C::NW), shmem, st, a);
   return hipGetLastError();
+}
+
+template <int H, int K, int PREC>
+static hipError_t launch_train_t(const TrainArgs& a, int n_wg, hipStream_t st) {
+  return a.sel ? launch_train_s<H, K, PREC, 1>(a, n_wg, st) : launch_train_s<H, K, PREC, 0>(a, n_wg, st);
 }
 
 hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st) {
@@ -363,7 +372,7 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const float bc1 = (float)(1.0 - pow((double)a.beta1, t));
   const float bc2_sqrt = (float)sqrt(1.0 - pow((double)a.beta2, t));
   const float step_size = a.lr / bc1;
-  const NetDims d{a.H, a.NH, a.K};
+  const NetDims d{a.H, a.NH, a.K, a.S};
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n_weights; i += (int64_t)gridDim.x * 256) {
     const float gi = a.grad[i];
     const float m = fmaf(a.beta1, a.m[i], (1.0f - a.beta1) * gi);
@@ -397,8 +406,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ w, 
   }
 }
 
-hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int prec, hipStream_t st) {
-  NetDims d{H, NH, K};
+hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int S, int prec, hipStream_t st) {
+  NetDims d{H, NH, K, S};
   int64_t n = prec == 1 ? Bf16Layout{d}.total_elems() : F32Layout{d}.total_elems();
   int grid = (int)((n + 255) / 256);
   if (grid > 1024) grid = 1024;

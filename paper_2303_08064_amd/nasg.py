@@ -38,15 +38,19 @@ class NasgGuide:
     """Device state of one guiding network plus its context in libnasg.so.
 
     weights: flat float32 canonical weights (W_0 [hidden][10], W_1..W_{n-1}
-    [hidden][hidden], W_L [8K][hidden], each row-major), e.g. from
+    [hidden][hidden], W_L [8K (+1)][hidden], each row-major), e.g. from
     synth.flat_weights(synth.init_weights(...)).
+    selection: the network has the selection-probability output and trains
+    on the blended loss with fraction mis_fraction (Sec. 4.2).
     """
 
     def __init__(self, weights, hidden=64, n_hidden=4, n_lobes=16, precision="bf16", eps=0.0,
-                 lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, device="cuda"):
+                 lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, device="cuda",
+                 selection=False, mis_fraction=0.2):
         self.lib = load()
         self.cfg = Config(hidden, n_hidden, n_lobes, PRECISIONS[precision], eps, lr, beta1, beta2,
-                          adam_eps, max_batch)
+                          adam_eps, max_batch, int(bool(selection)), mis_fraction)
+        self.selection = bool(selection)
         self.n_lobes = n_lobes
         self.hidden = hidden
         self.n_hidden = n_hidden
@@ -103,11 +107,17 @@ class NasgGuide:
     def forward_raw(self, feat, out=None):
         B, ld = _rows(feat, 9, "feat")
         if out is None:
-            out = torch.empty(8 * self.n_lobes, max(ld, 1), dtype=torch.float32, device=feat.device)
+            out = torch.empty(self.n_out, max(ld, 1), dtype=torch.float32, device=feat.device)
         check(self.lib.nasg_forward(self._ctx, _ptr(feat), ld, B, _ptr(out), self._stream()))
         return out[:, :B]
 
-    def query(self, feat, xi, dir_out=None, pdf_out=None, rec_out=None, records=False):
+    @property
+    def n_out(self):
+        return 8 * self.n_lobes + (1 if self.selection else 0)
+
+    def query(self, feat, xi, dir_out=None, pdf_out=None, rec_out=None, records=False, sel_out=None):
+        """(directions [3, B], pdf [B]) plus the records buffer when requested;
+        sel_out (a [B] tensor, selection networks only) receives c."""
         B, ld = _rows(feat, 9, "feat")
         Bx, ldx = _rows(xi, 4, "xi")
         if Bx != B or ldx != ld:
@@ -119,8 +129,10 @@ class NasgGuide:
             pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
         if records and rec_out is None:
             rec_out = torch.empty(max(record_elems(self.n_lobes, B), 1), dtype=torch.float32, device=dev)
+        if sel_out is not None and (sel_out.dtype != torch.float32 or sel_out.numel() < B):
+            raise ValueError("sel_out must be a float32 tensor of at least B elements")
         check(self.lib.nasg_query(self._ctx, _ptr(feat), _ptr(xi), ld, B, _ptr(dir_out), _ptr(pdf_out),
-                                  _ptr(rec_out), self._stream()))
+                                  _ptr(sel_out), _ptr(rec_out), self._stream()))
         if rec_out is not None:
             return dir_out[:, :B], pdf_out[:B], rec_out
         return dir_out[:, :B], pdf_out[:B]
@@ -143,31 +155,37 @@ class NasgGuide:
                                    self._stream()))
         return dir_out[:, :B], pdf_out[:B]
 
-    def _train_args(self, feat, dirs, w):
+    def _train_args(self, feat, dirs, w, bsdf_pdf):
         B, ld = _rows(feat, 9, "feat")
         Bd, ldd = _rows(dirs, 3, "dirs")
         if Bd != B or ldd != ld:
             raise ValueError("dirs must match feat in B and leading dimension")
-        if w.dtype != torch.float32 or w.dim() != 1 or w.shape[0] < B or w.stride(0) != 1:
-            raise ValueError("w must be a contiguous float32 [B] tensor")
+        for t, name in ((w, "w"), (bsdf_pdf, "bsdf_pdf")):
+            if t is None:
+                continue
+            if t.dtype != torch.float32 or t.dim() != 1 or t.shape[0] < B or t.stride(0) != 1:
+                raise ValueError(f"{name} must be a contiguous float32 [B] tensor")
         return B, ld
 
-    def loss_grad(self, feat, dirs, w):
-        """Writes self.grad and self.stats (loss, sum w, -, sum w*(-log q))."""
-        B, ld = self._train_args(feat, dirs, w)
-        check(self.lib.nasg_loss_grad(self._ctx, _ptr(feat), _ptr(dirs), _ptr(w), ld, B, self._stream()))
+    def loss_grad(self, feat, dirs, w, bsdf_pdf=None):
+        """Writes self.grad and self.stats (loss, sum w, -, sum w*(-log term)).
+        bsdf_pdf: p_fs at dirs, for selection networks (the blended loss)."""
+        B, ld = self._train_args(feat, dirs, w, bsdf_pdf)
+        check(self.lib.nasg_loss_grad(self._ctx, _ptr(feat), _ptr(dirs), _ptr(w), _ptr(bsdf_pdf), ld, B,
+                                      self._stream()))
 
     def adam_step(self):
         check(self.lib.nasg_adam_step(self._ctx, self._stream()))
 
-    def train_step(self, feat, dirs, w):
-        B, ld = self._train_args(feat, dirs, w)
-        check(self.lib.nasg_train_step(self._ctx, _ptr(feat), _ptr(dirs), _ptr(w), ld, B, self._stream()))
+    def train_step(self, feat, dirs, w, bsdf_pdf=None):
+        B, ld = self._train_args(feat, dirs, w, bsdf_pdf)
+        check(self.lib.nasg_train_step(self._ctx, _ptr(feat), _ptr(dirs), _ptr(w), _ptr(bsdf_pdf), ld, B,
+                                       self._stream()))
 
     # -- views -----------------------------------------------------------------
     def layer_shapes(self):
         s = [(self.hidden, 10)] + [(self.hidden, self.hidden)] * (self.n_hidden - 1)
-        return s + [(8 * self.n_lobes, self.hidden)]
+        return s + [(self.n_out, self.hidden)]
 
     def split(self, flat):
         """Flat canonical vector -> list of [out, in] views."""
@@ -176,6 +194,11 @@ class NasgGuide:
             out.append(flat[off:off + o * i].view(o, i))
             off += o * i
         return out
+
+
+def blend_ramp(frames_done, M=4, B=64):
+    """The blend ramp b of Sec. 5 (nasg_blend_ramp)."""
+    return float(load().nasg_blend_ramp(int(frames_done), int(M), int(B)))
 
 
 class NasgNLL(torch.autograd.Function):

@@ -52,10 +52,10 @@ def radiance_weights(n, rng):
     return np.exp(rng.standard_normal(n)).astype(np.float32)
 
 
-def layer_shapes(hidden, n_hidden, n_lobes):
+def layer_shapes(hidden, n_hidden, n_lobes, selection=False):
     shapes = [(hidden, IN_FEATURES + 1)]
     shapes += [(hidden, hidden)] * (n_hidden - 1)
-    shapes.append((8 * n_lobes, hidden))
+    shapes.append((8 * n_lobes + (1 if selection else 0), hidden))
     return shapes
 
 
@@ -198,3 +198,14 @@ def training_batch(n, rng, target):
     dirs = target.sample(feat[0:3].T.astype(np.float64), rng)
     w = radiance_weights(n, rng)
     return feat, dirs, w
+
+
+def lambert_pdf(dirs, normals):
+    """Cosine-weighted (Lambertian) BSDF sampling pdf max(0, d.n)/pi at unit
+    directions [3, B] (or [B, 3]) about unit normals of the same shape: the
+    p_fs a renderer would supply for a diffuse surface."""
+    d = np.asarray(dirs, dtype=np.float64)
+    n = np.asarray(normals, dtype=np.float64)
+    n = n / np.linalg.norm(n, axis=0 if d.shape[0] == 3 else -1, keepdims=True)
+    c = (d * n).sum(axis=0 if d.shape[0] == 3 else -1)
+    return (np.maximum(c, 0.0) / math.pi).astype(np.float32)

@@ -15,12 +15,17 @@ CONFIGS = {
     "c1_bf16": (64, 3, 4, "bf16"),
     "c5_bf16": (128, 4, 32, "bf16"),
     "c5_f32": (128, 4, 32, "f32"),
+    # with the selection-probability output (8K + 1 outputs, the blended loss)
+    "c2s_f32": (64, 4, 8, "f32"),
+    "c3s_bf16": (64, 4, 16, "bf16"),
+    "c1s_f32": (64, 3, 4, "f32"),
 }
+SELECTION = {"c2s_f32", "c3s_bf16", "c1s_f32"}
 
 
 def weights_for(name, seed=42, out_scale=1.0):
     H, NH, K, _ = CONFIGS[name]
-    mats = synth.init_weights(synth.layer_shapes(H, NH, K), synth.rng_for(seed))
+    mats = synth.init_weights(synth.layer_shapes(H, NH, K, selection=name in SELECTION), synth.rng_for(seed))
     mats[-1] = (mats[-1] * out_scale).astype(np.float32)
     return mats
 
@@ -29,6 +34,8 @@ def make_guide(name, seed=42, out_scale=1.0, max_batch=1 << 18, **kw):
     from paper_2303_08064_amd.nasg import NasgGuide
     H, NH, K, prec = CONFIGS[name]
     mats = weights_for(name, seed, out_scale)
+    if name in SELECTION:
+        kw.setdefault("selection", True)
     g = NasgGuide(synth.flat_weights(mats), hidden=H, n_hidden=NH, n_lobes=K, precision=prec,
                   max_batch=max_batch, **kw)
     return g, mats

@@ -8,8 +8,8 @@
 
 using namespace nasg;
 
-static int check_net(int H, int NH, int K) {
-  NetDims d{H, NH, K};
+static int check_net(int H, int NH, int K, int S) {
+  NetDims d{H, NH, K, S};
   const int64_t nw = d.num_weights();
   int bad = 0;
   // permutations are bijections
@@ -17,8 +17,10 @@ static int check_net(int H, int NH, int K) {
     if (phys_bf16(inv_phys_bf16(n)) != n) ++bad;
     if (phys_f32(inv_phys_f32(n)) != n) ++bad;
   }
-  for (int R = 0; R < 8 * K; ++R)
+  for (int R = 0; R < 8 * K + S; ++R)
     if (inv_canon_out_row(canon_out_row(R, K), K) != R) ++bad;
+  for (int R = 8 * K + S; R < d.out_rows(); ++R)
+    if (canon_out_row(R, K) != -1) ++bad;
   // bf16: gather source of every slot vs scatter position of every weight
   Bf16Layout bl{d};
   std::vector<int> seen_f(nw, 0), seen_b(nw, 0);
@@ -51,7 +53,7 @@ static int check_net(int H, int NH, int K) {
   }
   for (int64_t i = 0; i < nw; ++i)
     if (seen[i] != 1) ++bad;
-  printf("H=%d NH=%d K=%d weights=%lld bad=%d\n", H, NH, K, (long long)nw, bad);
+  printf("H=%d NH=%d K=%d S=%d weights=%lld bad=%d\n", H, NH, K, S, (long long)nw, bad);
   return bad;
 }
 
@@ -59,6 +61,7 @@ int main() {
   int bad = 0;
   for (int H : {64, 128})
     for (int NH : {1, 2, 3, 4})
-      for (int K : {4, 8, 16, 32}) bad += check_net(H, NH, K);
+      for (int K : {4, 8, 16, 32})
+        for (int S : {0, 1}) bad += check_net(H, NH, K, S);
   return bad != 0;
 }

@@ -1,0 +1,177 @@
+"""The selection-probability output and the blended loss (Sec. 4.2) on the
+GPU against the FP64 oracle, through the C ABI.
+
+Networks with 8K + 1 outputs: row 8K is the selection logit, c = sigmoid.
+The loss is e KL(p || q_hat) + (1 - e) KL(p || q), q_hat = c q + (1 - c) p_fs,
+estimated per sample with the weight w = p / q_hat (supplied) and the BSDF
+pdf p_fs at the training direction (supplied; here a Lambertian lobe about
+the vertex normal). Tolerances as in test_gpu_parity: FP32 raw outputs 1e-5
+per row; c 1e-6; loss 1e-5 relative; gradient 1e-4 stage-wise (the oracle's
+chain rule from the GPU's own raw outputs), 1e-3 end to end; BF16 against
+the oracle's BF16 emulation 2e-2 stage-wise.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from oracle import nasg as onasg
+from oracle import train as otrain
+from paper_2303_08064_amd import synth
+from tests.helpers import CONFIGS, make_guide, to_dev
+
+pytestmark = pytest.mark.gpu
+
+F64 = torch.float64
+E = 0.2
+
+
+def w64(mats):
+    return [torch.tensor(m, dtype=F64) for m in mats]
+
+
+def _batch(B, seed):
+    rng = synth.rng_for(seed)
+    feat, dirs, w = synth.training_batch(B, rng, synth.VmfTarget(4, seed=1001))
+    pdf = synth.lambert_pdf(dirs, feat[6:9])
+    return feat, dirs, w, pdf
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", ["c2s_f32", "c1s_f32", "c3s_bf16"])
+def test_forward_and_selection_output(name):
+    K, prec = CONFIGS[name][2], CONFIGS[name][3]
+    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E)
+    feat, _, _, _ = _batch(1000, 40)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    assert raw.shape[1] == 8 * K + 1
+    ref = omlp.forward(w64(mats), feat.T, bf16=prec == "bf16").numpy()
+    err = np.abs(raw - ref) / np.abs(ref).max(axis=1, keepdims=True)
+    if prec == "f32":
+        assert err.max() < 1e-5, err.max()
+    else:
+        assert np.mean(err < 1e-4) >= 0.999 and err.max() < 2e-2
+    # the query's selection probability is sigmoid(row 8K) of the same forward
+    xi = synth.uniforms(1000, synth.rng_for(41))
+    sel = torch.empty(1000, device="cuda")
+    d, pdf = g.query(to_dev(feat), to_dev(xi), sel_out=sel)
+    c_ref = onasg.selection(torch.tensor(raw), K).numpy()
+    assert np.abs(sel.cpu().numpy() - c_ref).max() < 1e-6
+    # directions and pdf are those of the 8K lobe outputs
+    lob = onasg.decode(torch.tensor(raw), K)
+    dd = d.cpu().numpy().T.astype(np.float64)
+    lq = onasg.mixture_log_pdf(torch.tensor(dd), lob).numpy()
+    assert np.median(np.abs(np.log(pdf.cpu().numpy()) - lq)) < 1e-5
+
+
+@pytest.mark.parametrize("name,B", [("c2s_f32", 1000), ("c1s_f32", 4096)])
+def test_blended_loss_grad_f32(name, B):
+    K = CONFIGS[name][2]
+    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E)
+    feat, dirs, w, pdf = _batch(B, 42)
+    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    torch.cuda.synchronize()
+    W = w64(mats)
+    L, grads = otrain.blended_loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
+    assert abs(float(g.stats[0]) - L) <= 1e-5 * abs(L), (float(g.stats[0]), L)
+    gg = [t.numpy() for t in g.split(g.grad.cpu())]
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    g_raw = otrain.blended_raw_output_grad(raw, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
+    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
+    errs = [_rel(a, b.numpy()) for a, b in zip(gg, staged)]
+    assert max(errs) < 1e-4, errs
+    # the selection row on its own (it is one row of the output layer)
+    assert _rel(gg[-1][-1], staged[-1][-1].numpy()) < 1e-4
+    errs_e2e = [_rel(a, b.numpy()) for a, b in zip(gg, grads)]
+    assert max(errs_e2e) < 1e-3, errs_e2e
+
+
+def test_blended_loss_grad_bf16():
+    name, K = "c3s_bf16", 16
+    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E)
+    feat, dirs, w, pdf = _batch(2048 + 35, 43)
+    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    torch.cuda.synchronize()
+    W = w64(mats)
+    L, grads = otrain.blended_loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K,
+                                            e=E, bf16=True)
+    assert abs(float(g.stats[0]) - L) <= 1e-3 * abs(L)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    g_raw = otrain.blended_raw_output_grad(raw, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
+    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw, bf16=True)
+    gg = [t.numpy() for t in g.split(g.grad.cpu())]
+    errs = [_rel(a, b.numpy()) for a, b in zip(gg, staged)]
+    assert max(errs) < 2e-2, errs
+    assert max(_rel(a, b.numpy()) for a, b in zip(gg, grads)) < 5e-2
+
+
+@pytest.mark.parametrize("name,base", [("c2s_f32", "c2_f32"), ("c3s_bf16", "c3_bf16")])
+def test_zero_fraction_matches_network_without_selection(name, base):
+    """e = 0: the selection row gets no gradient, and every other weight's
+    gradient and the loss equal those of the same network without the
+    selection output, bit for bit (the extra tile contributes exact zeros)."""
+    B = 3000
+    gs, mats = make_guide(name, out_scale=2.0, mis_fraction=0.0)
+    from paper_2303_08064_amd.nasg import NasgGuide
+    H, NH, K, prec = CONFIGS[base]
+    flat = synth.flat_weights(mats[:-1] + [mats[-1][:-1]])
+    gb = NasgGuide(flat, hidden=H, n_hidden=NH, n_lobes=K, precision=prec)
+    feat, dirs, w, pdf = _batch(B, 44)
+    gs.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    gb.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
+    torch.cuda.synchronize()
+    a, b = gs.split(gs.grad), gb.split(gb.grad)
+    assert torch.all(a[-1][-1] == 0)
+    for x, y in zip(a[:-1], b[:-1]):
+        assert torch.equal(x, y)
+    assert torch.equal(a[-1][:-1], b[-1])
+    assert torch.equal(gs.stats[:2], gb.stats[:2])
+
+
+@pytest.mark.parametrize("name", ["c2s_f32", "c3s_bf16"])
+def test_adam_repacks_selection_row(name):
+    """Adam updates the selection row and refreshes its packed copy: the
+    forward after three steps matches the oracle on the updated weights."""
+    K, prec = CONFIGS[name][2], CONFIGS[name][3]
+    g, _ = make_guide(name, mis_fraction=E)
+    feat, dirs, w, pdf = _batch(3000, 45)
+    for _ in range(3):
+        g.train_step(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    torch.cuda.synchronize()
+    assert int(g.step) == 3 and int(g.flags) == 0
+    f, _, _, _ = _batch(500, 46)
+    raw = g.forward_raw(to_dev(f)).cpu().numpy().T
+    ref = omlp.forward(g.split(g.w.cpu().double()), f.T, bf16=prec == "bf16").numpy()
+    err = np.abs(raw - ref) / np.abs(ref).max(axis=1, keepdims=True)
+    assert np.mean(err < 1e-4) > 0.995 and err.max() < 2e-2
+    assert np.abs(raw[:, 8 * K] - ref[:, 8 * K]).max() < 1e-2 * np.abs(ref[:, 8 * K]).max()
+
+
+def test_selection_training_is_deterministic():
+    outs = []
+    for _ in range(2):
+        g, _ = make_guide("c3s_bf16", mis_fraction=E)
+        feat, dirs, w, pdf = _batch(5000, 47)
+        for _ in range(3):
+            g.train_step(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+        torch.cuda.synchronize()
+        outs.append((g.w.clone(), g.stats.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_selection_argument_checks():
+    from paper_2303_08064_amd._lib import NasgError
+    g, _ = make_guide("c2s_f32")
+    feat, dirs, w, pdf = _batch(256, 48)
+    with pytest.raises(NasgError, match="bsdf_pdf"):
+        g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
+    g2, _ = make_guide("c2_f32")
+    with pytest.raises(NasgError, match="bsdf_pdf"):
+        g2.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    xi = synth.uniforms(256, synth.rng_for(49))
+    with pytest.raises(NasgError, match="sel_out"):
+        g2.query(to_dev(feat), to_dev(xi), sel_out=torch.empty(256, device="cuda"))

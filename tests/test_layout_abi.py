@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(lib):
 def _cfg(**kw):
     from paper_2303_08064_amd._lib import Config
     base = dict(hidden=64, n_hidden=4, n_lobes=16, precision=1, eps=0.0, lr=1e-3, beta1=0.9,
-                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18)
+                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, selection=0, mis_fraction=0.2)
     base.update(kw)
     return Config(**base)
 
@@ -84,4 +84,31 @@ def test_create_validates_on_host(lib):
     assert lib.nasg_create(ctypes.byref(_cfg(n_hidden=9)), ctypes.byref(st), ctypes.byref(ctx)) == NASG_E_ARG
     assert b"n_hidden" in lib.nasg_last_error()
     assert lib.nasg_create(ctypes.byref(_cfg(lr=-1.0)), ctypes.byref(st), ctypes.byref(ctx)) == NASG_E_ARG
-    assert lib.nasg_query(None, None, None, 0, 0, None, None, None, None) == NASG_E_ARG
+    assert lib.nasg_query(None, None, None, 0, 0, None, None, None, None, None) == NASG_E_ARG
+    # the selection output: hidden-64 networks only, mis_fraction in [0, 1]
+    assert lib.nasg_create(ctypes.byref(_cfg(hidden=128, n_lobes=32, selection=1)), ctypes.byref(st),
+                           ctypes.byref(ctx)) == NASG_E_ARG
+    assert b"selection" in lib.nasg_last_error()
+    assert lib.nasg_create(ctypes.byref(_cfg(selection=1, mis_fraction=1.5)), ctypes.byref(st),
+                           ctypes.byref(ctx)) == NASG_E_ARG
+    assert b"mis_fraction" in lib.nasg_last_error()
+
+
+def test_selection_sizes(lib):
+    """8K + 1 outputs: 64 more weights; the BF16 packing adds one 16-row
+    forward tile and 16 x 64 16x16x16 backward elements, FP32 one padded
+    16-row block."""
+    c = _cfg(selection=1)
+    assert lib.nasg_num_weights(ctypes.byref(c)) == 21120 + 64
+    assert lib.nasg_packed_bytes(ctypes.byref(c)) == 2 * (1024 + 3 * 4096 + 144 * 64 + 3 * 4096 + 8192 + 16 * 64)
+    c32 = _cfg(precision=0, n_lobes=8, selection=1)
+    assert lib.nasg_packed_bytes(ctypes.byref(c32)) == 4 * (64 * 17 + 3 * 64 * 65 + 80 * 65)
+
+
+def test_blend_ramp_matches_oracle(lib):
+    """nasg_blend_ramp (host) against the oracle's ramp of Sec. 5."""
+    from oracle import train
+    for n in (0, 1, 3, 4, 5, 63, 64, 100, 255, 256, 257, 10 ** 6):
+        assert abs(lib.nasg_blend_ramp(n, 4, 64) - train.blend_ramp(n)) < 1e-7
+    assert lib.nasg_blend_ramp(9, 3, 2) == train.blend_ramp(9, M=3, B=2) == 1.0
+    assert lib.nasg_blend_ramp(-5, 4, 64) == 0.0 and lib.nasg_blend_ramp(10, 0, 64) == 0.0

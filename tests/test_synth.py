@@ -56,3 +56,15 @@ def test_aniso_target_shapes():
     v = t.sample(rng.random((1000, 3)), rng)
     assert v.shape == (3, 1000) and np.allclose(np.linalg.norm(v, axis=0), 1, atol=1e-6)
     assert t.sig_major.max() <= 0.8 and (t.sig_major / t.sig_minor).max() <= 20 + 1e-9
+
+
+def test_lambert_pdf_is_a_density():
+    """max(0, d.n)/pi integrates to one over the sphere (Monte Carlo with
+    uniform directions) and vanishes below the surface."""
+    rng = synth.rng_for(5)
+    d = synth.unit_vectors(400000, rng).T
+    n = np.tile(np.array([[0.3], [-0.5], [0.81]]), (1, d.shape[1]))
+    p = synth.lambert_pdf(d, n).astype(np.float64)
+    assert abs(np.mean(p) * 4 * np.pi - 1.0) < 5e-3
+    nn = n / np.linalg.norm(n, axis=0)
+    assert np.all(p[(d * nn).sum(0) < 0] == 0)
