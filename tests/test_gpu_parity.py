@@ -350,3 +350,63 @@ def test_record_round_trip_layout():
     a = np.random.default_rng(0).standard_normal((130, 8, 9)).astype(np.float32)
     back = rec_to_bk9(torch.from_numpy(bk9_to_rec(a, 8)), 130, 8)
     assert np.array_equal(back.astype(np.float32), a)
+
+
+# ---- the continuous form of App. A (epsilon > 0) ----
+
+EPS = 0.3
+
+
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
+def test_query_records_pdf_sample_eps(name):
+    """epsilon = 0.3: decoded records (log K with epsilon), the pdf at the
+    sampled direction, and the record kernels, against the oracle's
+    App. A lobe on the GPU's own raw outputs."""
+    K = CONFIGS[name][2]
+    g, mats = make_guide(name, out_scale=3.0, eps=EPS)
+    feat, xi = inputs(B_RAGGED, 21)
+    d, pdf, rec = g.query(to_dev(feat), to_dev(xi), records=True)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    lob = onasg.decode(torch.tensor(raw), K, EPS)
+    recg = rec_to_bk9(rec, B_RAGGED, K)
+    ro = lob.record().numpy()
+    assert np.abs(recg[..., 0:6] - ro[..., 0:6]).max() < 1e-6
+    assert np.abs(recg[..., 8] - ro[..., 8]).max() < 1e-5
+    dd = d.cpu().numpy().T.astype(np.float64)
+    lq = onasg.mixture_log_pdf(torch.tensor(dd), lob).numpy()
+    assert np.abs(np.log(pdf.cpu().numpy()) - lq).max() < 1e-4   # continuous: no -z exclusion needed
+    vo, _ = onasg.sample(lob, xi.T.astype(np.float64))
+    keep = cdf_margin(lob, xi[0]) > 1e-5
+    assert np.linalg.norm(dd - vo.numpy(), axis=1)[keep].max() < 1e-4
+    # record kernels with the same epsilon
+    uni = synth.unit_vectors(B_RAGGED, synth.rng_for(22)).T.astype(np.float32)
+    pg = g.pdf(rec, to_dev(np.ascontiguousarray(uni))).cpu().numpy().astype(np.float64)
+    lobr = onasg.lobes_from_record(recg, EPS)
+    lq2 = onasg.mixture_log_pdf(torch.tensor(uni.T.astype(np.float64)), lobr).numpy()
+    assert np.abs(np.log(pg) - lq2).max() < 1e-4
+    xi2 = synth.uniforms(B_RAGGED, synth.rng_for(23))
+    d2, p2 = g.sample(rec, to_dev(xi2))
+    vs, _ = onasg.sample_from_record(recg, xi2.T.astype(np.float64), EPS)
+    d2 = d2.cpu().numpy().T.astype(np.float64)
+    full = onasg.Lobes(z=lobr.z, x=lobr.x, y=lobr.y, lam=lobr.lam, a=lobr.a,
+                       log_A=lobr.log_A + onasg.log_normaliser(lobr.lam, lobr.a, EPS),
+                       log_K=torch.zeros_like(lobr.a), eps=EPS)
+    keep2 = cdf_margin(full, xi2[0]) > 1e-5
+    assert np.linalg.norm(d2 - vs.numpy(), axis=1)[keep2].max() < 1e-4
+
+
+def test_loss_grad_f32_eps():
+    """epsilon = 0.3 in the training path: loss and stage-wise gradient."""
+    name, K = "c2_f32", 8
+    g, mats = make_guide(name, out_scale=2.0, eps=EPS)
+    feat, dirs, w = _train_batch(B_RAGGED, 24)
+    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
+    torch.cuda.synchronize()
+    W = w64(mats)
+    L, grads = otrain.loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), K, EPS)
+    assert abs(float(g.stats[0]) - L) <= 1e-5 * abs(L)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    g_raw = otrain.raw_output_grad(raw, dirs.T, w.astype(np.float64), K, EPS)
+    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
+    errs = _rel_errors(g.split(g.grad.cpu()), staged)
+    assert max(errs) < 1e-4, errs
