@@ -159,6 +159,18 @@ def mixture_log_pdf(v, lobes):
     return torch.logsumexp(component_log_terms(v, lobes), dim=-1)
 
 
+def log_pdf_direction_grad(v, lobes):
+    """Gradient of log D with respect to the direction, on the sphere [B, 3].
+
+    D is evaluated at v / |v| (as ``mixture_log_pdf`` does), so at a unit v
+    the float64 autograd gradient is the tangential one, (I - v v^T) times
+    the Euclidean gradient of any extension of log D off the sphere.
+    """
+    v = torch.as_tensor(v, dtype=F64).clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(mixture_log_pdf(v, lobes).sum(), v)
+    return g.detach()
+
+
 def choose_lobe(log_A, xi_sel):
     """Inverse-CDF choice of a mixture component (reading; the paper is silent).
 
