@@ -133,6 +133,16 @@ nasg_status nasg_query(nasg_ctx* ctx, const float* feat, const float* xi, int64_
 nasg_status nasg_pdf(nasg_ctx* ctx, const float* rec, const float* dir, int64_t ld, int64_t B,
                      float* pdf_out, void* stream);
 
+/* Mixture pdf and the gradient of log D with respect to the direction, from
+ * decoded records (eq. NASG; App. A when eps > 0), for downstream uses such as
+ * MIS weights over a solid-angle neighbourhood or denoising:
+ *   dir      [3][ld] directions (normalised inside)
+ *   pdf_out  [B]
+ *   grad_out [3][ld] the gradient on the sphere at dir/|dir| (tangent to it;
+ *            the Euclidean gradient of log D(d/|d|) at a unit d). */
+nasg_status nasg_pdf_grad(nasg_ctx* ctx, const float* rec, const float* dir, int64_t ld, int64_t B,
+                          float* pdf_out, float* grad_out, void* stream);
+
 /* Direct sampling from decoded records (App. C), with the inverse-CDF lobe
  * choice of nasg_query; writes the direction and the mixture pdf there. */
 nasg_status nasg_sample(nasg_ctx* ctx, const float* rec, const float* xi, int64_t ld, int64_t B,

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "NASG_OK", 1: "NASG_E_ARG", 2: "NASG_E_SHAPE", 3: "NASG_E_ALI
 EXPORTED = [
     "nasg_num_weights", "nasg_packed_bytes", "nasg_workspace_bytes", "nasg_create", "nasg_destroy",
     "nasg_last_error", "nasg_pack", "nasg_forward", "nasg_query", "nasg_pdf", "nasg_sample",
-    "nasg_loss_grad", "nasg_adam_step", "nasg_train_step", "nasg_blend_ramp",
+    "nasg_loss_grad", "nasg_adam_step", "nasg_train_step", "nasg_blend_ramp", "nasg_pdf_grad",
 ]
 
 
@@ -72,6 +72,7 @@ def load():
         "nasg_query": (S, [P, P, P, I64, I64, P, P, P, P, P]),
         "nasg_pdf": (S, [P, P, P, I64, I64, P, P]),
         "nasg_sample": (S, [P, P, P, I64, I64, P, P, P]),
+        "nasg_pdf_grad": (S, [P, P, P, I64, I64, P, P, P]),
         "nasg_loss_grad": (S, [P, P, P, P, P, I64, I64, P]),
         "nasg_adam_step": (S, [P, P]),
         "nasg_train_step": (S, [P, P, P, P, P, I64, I64, P]),

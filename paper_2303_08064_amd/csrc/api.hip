@@ -267,8 +267,23 @@ nasg_status nasg_pdf(nasg_ctx* ctx, const float* rec, const float* dir, int64_t 
   NASG_TRY(check_ptr(fn, rec, "rec"));
   NASG_TRY(check_ptr(fn, dir, "dir"));
   NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
-  RecArgs a{rec, dir, nullptr, ld, B, ctx->cfg.eps, nullptr, pdf_out};
+  RecArgs a{rec, dir, nullptr, ld, B, ctx->cfg.eps, nullptr, pdf_out, nullptr};
   hipError_t e = launch_pdf(a, ctx->d.K, (hipStream_t)stream);
+  return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
+}
+
+nasg_status nasg_pdf_grad(nasg_ctx* ctx, const float* rec, const float* dir, int64_t ld, int64_t B,
+                          float* pdf_out, float* grad_out, void* stream) {
+  static const char* fn = "nasg_pdf_grad";
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  NASG_TRY(check_batch(fn, ld, B));
+  if (B == 0) return NASG_OK;
+  NASG_TRY(check_ptr(fn, rec, "rec"));
+  NASG_TRY(check_ptr(fn, dir, "dir"));
+  NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
+  NASG_TRY(check_ptr(fn, grad_out, "grad_out"));
+  RecArgs a{rec, dir, nullptr, ld, B, ctx->cfg.eps, nullptr, pdf_out, grad_out};
+  hipError_t e = launch_pdf_grad(a, ctx->d.K, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
@@ -282,7 +297,7 @@ nasg_status nasg_sample(nasg_ctx* ctx, const float* rec, const float* xi, int64_
   NASG_TRY(check_ptr(fn, xi, "xi"));
   NASG_TRY(check_ptr(fn, dir_out, "dir_out"));
   NASG_TRY(check_ptr(fn, pdf_out, "pdf_out"));
-  RecArgs a{rec, nullptr, xi, ld, B, ctx->cfg.eps, dir_out, pdf_out};
+  RecArgs a{rec, nullptr, xi, ld, B, ctx->cfg.eps, dir_out, pdf_out, nullptr};
   hipError_t e = launch_sample(a, ctx->d.K, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }

@@ -41,6 +41,7 @@ struct RecArgs {
   float eps;
   float* dir_out;
   float* pdf_out;
+  float* grad_out;    // pdf_grad: [3][ld] gradient of log D on the sphere
 };
 
 struct TrainArgs {
@@ -172,6 +173,7 @@ __device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
 hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
 hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
+hipError_t launch_pdf_grad(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
 hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
 hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, int n_grad,

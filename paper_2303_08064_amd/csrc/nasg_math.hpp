@@ -231,6 +231,30 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   return r;
 }
 
+// Euclidean gradient with respect to v of ell = log c + log G (eq. NASG; App.
+// A) at a unit v, through v.z, X = v.x and Y = v.y (the same partials as
+// backward_lobe): d ell/d(v.z) = (2 lam p u^p + p - 1) / (2u) and, with
+// d ell/dp = log u (2 lam u^p + 1), the anisotropy c^2 = X^2 / (X^2 + Y^2)
+// contributes a d ell/dp (2 X Y^2, -2 Y X^2) / (X^2 + Y^2)^2. Zero where the
+// lobe vanishes (v = -z). Callers project onto the tangent plane of the
+// sphere, where any extension of the lobe off the sphere has this gradient.
+__device__ __forceinline__ void dir_grad_lobe(const Lobe& L, const Eval& e, float& gx, float& gy, float& gz) {
+  const bool live = e.u > 0.0f;
+  const float epl = e.E + 1.0f;   // u^p
+  const float twolam = 2.0f * L.lam;
+  const float GZ = fsel(live, fmaf(twolam * e.p, epl, e.p - 1.0f) * frcp(2.0f * e.u), 0.0f);
+  const float Dp = e.L * fmaf(twolam, epl, 1.0f);
+  const float invS = frcp(e.S);
+  const float coef = fsel(live && e.S > 0.0f, L.a * Dp * 2.0f * invS * invS, 0.0f);
+  const float GX = coef * e.X * e.Y * e.Y;
+  const float GY = -coef * e.Y * e.X * e.X;
+  float yx, yy, yz;
+  cross(L.zx, L.zy, L.zz, L.xx, L.xy, L.xz, yx, yy, yz);
+  gx = fmaf(GZ, L.zx, fmaf(GX, L.xx, GY * yx));
+  gy = fmaf(GZ, L.zy, fmaf(GX, L.xy, GY * yy));
+  gz = fmaf(GZ, L.zz, fmaf(GX, L.xz, GY * yz));
+}
+
 // One direction from a single lobe (App. C): (xi0, xi1) -> (s, rho) linearly,
 // xi2 > 1/2 east. Stable form: log s = log(1 + (1 - xi0)(e^{-2 lam} - 1)),
 // (cos theta + 1)/2 = (1 + log s / (2 lam))^{1/p} with p = 1 + eps + a cos^2 phi,

@@ -92,6 +92,53 @@ __global__ __launch_bounds__(256) void sample_kernel(RecArgs a) {
   a.pdf_out[v] = fexp(log_mixture<K>(lb, vx, vy, vz, a.eps));
 }
 
+// Mixture pdf and the gradient of log D with respect to the direction on the
+// sphere: sum_k r_k grad ell_k with r_k = D_k / D, minus its component along v.
+template <int K>
+__global__ __launch_bounds__(256) void pdf_grad_kernel(RecArgs a) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= a.B) return;
+  float vx = a.dir[v], vy = a.dir[a.ld + v], vz = a.dir[2 * a.ld + v];
+  float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+  vx *= inv; vy *= inv; vz *= inv;
+  Lobe lb[K];
+  load_records<K>(a.rec, v, lb);
+  const float logq = log_mixture<K>(lb, vx, vy, vz, a.eps);
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const Eval e = eval_lobe(lb[k], vx, vy, vz, a.eps);
+    const float r = fexp(e.ell - logq);
+    float hx, hy, hz;
+    dir_grad_lobe(lb[k], e, hx, hy, hz);
+    gx = fmaf(r, hx, gx);
+    gy = fmaf(r, hy, gy);
+    gz = fmaf(r, hz, gz);
+  }
+  const float dot = fmaf(gx, vx, fmaf(gy, vy, gz * vz));
+  a.pdf_out[v] = fexp(logq);
+  a.grad_out[v] = fmaf(-dot, vx, gx);
+  a.grad_out[a.ld + v] = fmaf(-dot, vy, gy);
+  a.grad_out[2 * a.ld + v] = fmaf(-dot, vz, gz);
+}
+
+template <int K>
+static hipError_t launch_pdf_grad_t(const RecArgs& a, hipStream_t st) {
+  int grid = (int)((a.B + 255) / 256);
+  hipLaunchKernelGGL(pdf_grad_kernel<K>, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pdf_grad(const RecArgs& a, int K, hipStream_t st) {
+  switch (K) {
+    case 4: return launch_pdf_grad_t<4>(a, st);
+    case 8: return launch_pdf_grad_t<8>(a, st);
+    case 16: return launch_pdf_grad_t<16>(a, st);
+    case 32: return launch_pdf_grad_t<32>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int K>
 static hipError_t launch_pdf_t(const RecArgs& a, hipStream_t st) {
   int grid = (int)((a.B + 255) / 256);

@@ -144,6 +144,18 @@ class NasgGuide:
         check(self.lib.nasg_pdf(self._ctx, _ptr(rec), _ptr(dirs), ld, B, _ptr(pdf_out), self._stream()))
         return pdf_out[:B]
 
+    def pdf_grad(self, rec, dirs, pdf_out=None, grad_out=None):
+        """(pdf [B], gradient of log pdf on the sphere [3, B]) at dirs."""
+        B, ld = _rows(dirs, 3, "dirs")
+        dev = dirs.device
+        if pdf_out is None:
+            pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        if grad_out is None:
+            grad_out = torch.empty(3, max(ld, 1), dtype=torch.float32, device=dev)
+        check(self.lib.nasg_pdf_grad(self._ctx, _ptr(rec), _ptr(dirs), ld, B, _ptr(pdf_out), _ptr(grad_out),
+                                     self._stream()))
+        return pdf_out[:B], grad_out[:, :B]
+
     def sample(self, rec, xi, dir_out=None, pdf_out=None):
         B, ld = _rows(xi, 4, "xi")
         dev = xi.device

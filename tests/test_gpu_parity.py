@@ -410,3 +410,35 @@ def test_loss_grad_f32_eps():
     staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
     errs = _rel_errors(g.split(g.grad.cpu()), staged)
     assert max(errs) < 1e-4, errs
+
+
+@pytest.mark.parametrize("name,eps", [("c2_f32", 0.0), ("c3_bf16", 0.0), ("c3_bf16", 0.3), ("c5_bf16", 0.0)])
+def test_pdf_direction_gradient(name, eps):
+    """nasg_pdf_grad: the pdf as nasg_pdf, and the gradient of log D on the
+    sphere against the oracle's autograd gradient, from the same records;
+    per vertex within 1e-4 of the gradient's scale (|grad| + 1) away from
+    the lobe axes. Within 0.05 rad of a lobe's z or -z the FP32 evaluation
+    is ill-conditioned: the anisotropy c^2 = X^2 / (X^2 + Y^2) is 0/0 there
+    (X, Y carry ~1e-7 absolute rounding) and at -z the eps = 0 lobe's
+    gradient diverges like u^(a c^2 - 1); those vertices (a few percent) are
+    held to 1e-2."""
+    K = CONFIGS[name][2]
+    g, _ = make_guide(name, out_scale=3.0, eps=eps)
+    feat, xi = inputs(B_RAGGED, 25)
+    _, _, rec = g.query(to_dev(feat), to_dev(xi), records=True)
+    uni = np.ascontiguousarray(synth.unit_vectors(B_RAGGED, synth.rng_for(26)).T.astype(np.float32))
+    pdf, grad = g.pdf_grad(rec, to_dev(uni))
+    lob = onasg.lobes_from_record(rec_to_bk9(rec, B_RAGGED, K), eps)
+    v = torch.tensor(uni.T.astype(np.float64))
+    lq = onasg.mixture_log_pdf(v, lob).numpy()
+    gr = onasg.log_pdf_direction_grad(v, lob).numpy()
+    gg = grad.cpu().numpy().T.astype(np.float64)
+    vz = (v[:, None, :] * lob.z).sum(-1).numpy()
+    ok = ~((np.abs(vz) > np.cos(5e-2)).any(-1))
+    assert ok.mean() > 0.9
+    near_minus_z_ = (vz < -np.cos(1e-3)).any(-1)
+    assert np.abs(np.log(pdf.cpu().numpy()) - lq)[~near_minus_z_].max() < 1e-4
+    err = np.linalg.norm(gg - gr, axis=1) / (np.linalg.norm(gr, axis=1) + 1.0)
+    assert err[ok].max() < 1e-4, err[ok].max()
+    assert err[~near_minus_z_].max() < 1e-2, err[~near_minus_z_].max()
+    assert np.abs((gg * uni.T).sum(1)).max() < 1e-4 * (np.abs(gg).max() + 1)
