@@ -62,7 +62,28 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
                                                 float pdf_bsdf = 0.0f, float mis_e = 0.0f) {
   constexpr int TS = 2 * KQ;   // the selection tile (S = 1)
   static_assert(MTO == 2 * KQ + S, "output tiles: 8K rows plus the selection tile");
-  const float lse = logit_lse<KQ, MTO>(out);
+  // softmax of the K logits: A_k = e^{alpha_k - m} / sum, kept for the logit gradient
+  float ea[KQ];
+  float lse, inv_se;
+  {
+    float mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int t = 7 * KQ + q;
+      mx = fmaxf(mx, out[t >> 2][t & 3]);
+    }
+    mx = quad_max(mx);
+    float se = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int t = 7 * KQ + q;
+      ea[q] = fexp(out[t >> 2][t & 3] - mx);
+      se += ea[q];
+    }
+    se = quad_sum(se);
+    lse = mx + flog(se);
+    inv_se = frcp(se);
+  }
   float ell[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
@@ -102,7 +123,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
   for (int q = 0; q < KQ; ++q) {
     const int t7 = 7 * KQ + q;
     const float r = valid ? fexp(ell[q] - logq) : 0.0f;
-    const float Aq = fexp(out[t7 >> 2][t7 & 3] - lse);
+    const float Aq = ea[q] * inv_se;
     const float sc = gsq * r;
 #pragma unroll
     for (int p = 0; p < 7; ++p) {

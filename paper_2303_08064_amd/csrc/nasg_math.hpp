@@ -195,6 +195,7 @@ struct Eval {
   float E;        // expm1(p L) = u^p - 1
   float p, c2;    // exponent and anisotropy weight
   float X, Y, S;  // v.x, v.y, X^2 + Y^2
+  float invS;     // 1 / S (used again by the derivatives)
 };
 
 __device__ __forceinline__ void cross(float ax, float ay, float az, float bx, float by, float bz,
@@ -222,7 +223,8 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   r.X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
   r.Y = fmaf(vx, yx, fmaf(vy, yy, vz * yz));
   r.S = fmaf(r.X, r.X, r.Y * r.Y);
-  r.c2 = fsel(r.S > 0.0f, r.X * r.X * frcp(r.S), 0.0f);
+  r.invS = frcp(r.S);
+  r.c2 = fsel(r.S > 0.0f, r.X * r.X * r.invS, 0.0f);
   r.p = 1.0f + eps + L.a * r.c2;
   r.E = expm1f_(r.p * r.L);
   float lg = fmaf(2.0f * L.lam, r.E, (r.p - 1.0f) * r.L);
@@ -244,8 +246,7 @@ __device__ __forceinline__ void dir_grad_lobe(const Lobe& L, const Eval& e, floa
   const float twolam = 2.0f * L.lam;
   const float GZ = fsel(live, fmaf(twolam * e.p, epl, e.p - 1.0f) * frcp(2.0f * e.u), 0.0f);
   const float Dp = e.L * fmaf(twolam, epl, 1.0f);
-  const float invS = frcp(e.S);
-  const float coef = fsel(live && e.S > 0.0f, L.a * Dp * 2.0f * invS * invS, 0.0f);
+  const float coef = fsel(live && e.S > 0.0f, L.a * Dp * 2.0f * e.invS * e.invS, 0.0f);
   const float GX = coef * e.X * e.Y * e.Y;
   const float GY = -coef * e.Y * e.X * e.X;
   float yx, yy, yz;
@@ -317,8 +318,7 @@ __device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, c
   // direction terms
   float DL = fmaf(twolam * e.p, epl, e.p - 1.0f);
   float gZ = fsel(live, gk * DL * frcp(2.0f * e.u), 0.0f);
-  float invS = frcp(e.S);
-  float coef = fsel(live && e.S > 0.0f, gk * L.a * Dp * 2.0f * invS * invS, 0.0f);
+  float coef = fsel(live && e.S > 0.0f, gk * L.a * Dp * 2.0f * e.invS * e.invS, 0.0f);
   float gX = coef * e.X * e.Y * e.Y;
   float gY = -coef * e.Y * e.X * e.X;
   // X = ctau R + stau Q, Y = -stau R + ctau Q, Zc = st P + ct vz, R = ct P - st vz
