@@ -323,24 +323,6 @@ __device__ __forceinline__ void stage_act(S* st, const Act<PREC, MTH>& h, int wa
   stage_rows<S, MTH, SP>(st, x, wave, lane);
 }
 
-// Layer 0's input (features, the constant one, zero padding) of the tile's
-// 64 vertices as staging columns k = 0..15.
-template <typename S, int SP>
-__device__ __forceinline__ void stage_input(S* st, const float* feat, int64_t ld, int64_t v, bool valid, int wave,
-                                            int lane) {
-  const int g = lane >> 4, c = lane & 15;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int k = 4 * g + j;
-    float xv = 0.0f;
-    if (valid) {
-      if (k < kInFeatures) xv = feat[(int64_t)k * ld + v];
-      else if (k == kInFeatures) xv = 1.0f;
-    }
-    st[k * SP + wave * 16 + c] = (S)xv;
-  }
-}
-
 // dL/d(raw outputs) of 16 vertices: BF16 as the output layer's dgrad B
 // operands (K/4 16-byte slots per lane); FP32 as the accumulator image
 // (K/2 16-byte slots per lane).
@@ -669,7 +651,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
         W* t = cur; cur = oth; oth = t;
       }
       d2w.template stage<SP>(dst, wave, lane);
-      stage_input<S, SP>(hst, a.feat, a.ld, v, valid, wave, lane);
+      M::template stage_input<S, SP>(hst, x, wave, lane);
       __syncthreads();
       wgrad_tiles<1, S, SP, 1, 1, kBwdV>(dst, hst, rt, 1, acc0, lane);
       b0 = cur;   // the next tile's layer 0
@@ -802,7 +784,7 @@ void bwd_f32_kernel(LargeTrainArgs a) {
           for (int i = 0; i < 4; ++i) d2[mt][i] = dn[mt][i];
       }
       stage_rows<S, MTH, SP>(dst, d2, wave, lane);
-      stage_input<S, SP>(hst, a.feat, a.ld, v, valid, wave, lane);
+      M::template stage_input<S, SP>(hst, x, wave, lane);
       __syncthreads();
       wgrad_tiles<0, S, SP, RTW_H, 1>(dst, hst, rt_h, nrt_h, acc0, lane);
       __syncthreads();

@@ -39,6 +39,15 @@ struct Mlp<H, K, 1> {
     return bf16x4{(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
   }
 
+  // layer 0's input (the values the forward used) into rows 0..15 of a
+  // [row][vertex] staging buffer at vertex column wave*16: rows 4g..4g+3
+  template <typename S, int SP>
+  __device__ static void stage_input(S* st, const Input& x, int wave, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[(4 * g + j) * SP + wave * 16 + c] = (S)x[j];
+  }
+
   __device__ static bf16x8 operand(const float (&in)[2][4]) {
     bf16x8 b;
 #pragma unroll
@@ -147,6 +156,16 @@ struct Mlp<H, K, 0> {
       in.x[kb] = x;
     }
     return in;
+  }
+
+  // layer 0's input into rows 0..15 of a staging buffer: rows kb*4 + g hold
+  // this lane's x.x[kb], rows 12..15 are zero padding
+  template <typename S, int SP>
+  __device__ static void stage_input(S* st, const Input& x, int wave, int lane) {
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb) st[(kb * 4 + g) * SP + wave * 16 + c] = (S)x.x[kb];
+    st[(12 + g) * SP + wave * 16 + c] = (S)0.0f;
   }
 
   __device__ static void layer0(const float* lds, const Input& x, float (&h)[MTH][4], int lane) {

@@ -101,23 +101,42 @@ void train_kernel(TrainArgs a) {
   double loss_sum = 0.0, w_sum = 0.0;
 
   const int64_t n_tiles = (a.B + NV - 1) / NV;
+  // this vertex's inputs, loaded one tile ahead so that their latency
+  // overlaps the previous tile's work
+  struct In {
+    typename M::Input x;
+    float dx, dy, dz, w, pfs;
+  };
+  auto load_in = [&](int64_t vv) {
+    In r;
+    const bool ok = vv < a.B;
+    r.x = M::load_input(a.feat, a.ld, vv, ok, g);
+    r.dx = 0.0f; r.dy = 0.0f; r.dz = 1.0f; r.w = 0.0f; r.pfs = 0.0f;
+    if (ok) {
+      r.dx = a.dir[vv]; r.dy = a.dir[a.ld + vv]; r.dz = a.dir[2 * a.ld + vv];
+      r.w = a.w[vv];
+      if (SEL == 1) r.pfs = a.bsdf_pdf[vv];
+    }
+    return r;
+  };
+  In nxt = load_in((int64_t)blockIdx.x * NV + wave * 16 + c);
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * NV + wave * 16 + c;
     const bool valid = v < a.B;
+    const In cur = nxt;
+    if (tile + gridDim.x < n_tiles) nxt = load_in((tile + gridDim.x) * NV + wave * 16 + c);
     // ---- forward (recomputed) ----
-    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    const typename M::Input x = cur.x;
     float h[NHMAX][MTH][4];
     float last[MTH][4];
     float out[MTO][4];
     Forward<H, K, PREC, NHMAX, SEL>::run(lds, nh, x, h, last, out, lane);
 
     // ---- weighted NLL and its gradient w.r.t. the raw outputs ----
-    float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f, pfs = 0.0f;
-    if (valid) {
-      vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
-      wj = a.w[v];
-      if (SEL == 1) pfs = a.bsdf_pdf[v];
-      float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    float vx = cur.dx, vy = cur.dy, vz = cur.dz;
+    const float wj = cur.w, pfs = cur.pfs;
+    {
+      const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
     }
     const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q (of the log term)
@@ -170,17 +189,7 @@ void train_kernel(TrainArgs a) {
     // ---- layer 0: input = features, constant one, zero padding ----
     {
       stage_rows<S, MTH, SP>(dst, dh, wave, lane);
-      // input rows 0..15 for this wave's 16 vertices: lane (g, c) writes rows 4g..4g+3
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
-        float xv = 0.0f;
-        if (valid) {
-          if (k < kInFeatures) xv = a.feat[(int64_t)k * a.ld + v];
-          else if (k == kInFeatures) xv = 1.0f;
-        }
-        hst[k * SP + wave * 16 + c] = (S)xv;
-      }
+      M::template stage_input<S, SP>(hst, x, wave, lane);
       __syncthreads();
       wgrad_own<PREC, S, SP, MTH, 1, NW, NV>(dst, hst, acc0, wave, lane);
       __syncthreads();
