@@ -264,12 +264,14 @@ hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hi
 // ---------------------------------------------------------------- reduce ----
 // grad[i] = sum over workgroups of partial[wg][i] in a fixed order: thread
 // group q (of 16) of a block sums workgroups q, q+16, q+32, ... for four
-// consecutive weights with 16-byte loads (eight in flight, FP64 sums), then
-// the 16 group sums are added in order. Each block also writes its FP64 sum
-// of grad^2; block 0 totals the loss. n_weights is a multiple of 4 for every
-// compiled network (checked on the host).
+// consecutive weights with 16-byte loads (all of them in flight, FP64 sums),
+// then the 16 group sums are added in order. Each block also writes its FP64
+// sum of grad^2; block 0 totals the loss partials (strided per thread, then
+// a fixed tree). n_weights is a multiple of 4 for every compiled network
+// (checked on the host); at most 256 workgroup partials, 512 loss partials.
 constexpr int kRedW = 64;   // weights per block
 constexpr int kRedQ = 16;   // workgroup groups per block
+constexpr int kRedT = kMaxTrainWG / kRedQ;   // partial rows per group
 
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const int j = threadIdx.x & 15, q = threadIdx.x >> 4;
@@ -277,23 +279,21 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   if (i0 < a.n_weights) {
     const float* p = a.partial + i0;
-    int wg = q;
-    for (; wg + 7 * kRedQ < a.n_wg; wg += 8 * kRedQ) {
-      float4 x[8];
+    float4 x[kRedT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const float4*>(p + (int64_t)(wg + u * kRedQ) * a.n_weights);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        s[0] += (double)x[u].x; s[1] += (double)x[u].y; s[2] += (double)x[u].z; s[3] += (double)x[u].w;
-      }
+    for (int t = 0; t < kRedT; ++t) {
+      const int wg = q + kRedQ * t;
+      x[t] = wg < a.n_wg ? *reinterpret_cast<const float4*>(p + (int64_t)wg * a.n_weights)
+                         : float4{0.0f, 0.0f, 0.0f, 0.0f};
     }
-    for (; wg < a.n_wg; wg += kRedQ) {
-      const float4 x = *reinterpret_cast<const float4*>(p + (int64_t)wg * a.n_weights);
-      s[0] += (double)x.x; s[1] += (double)x.y; s[2] += (double)x.z; s[3] += (double)x.w;
+#pragma unroll
+    for (int t = 0; t < kRedT; ++t) {
+      s[0] += (double)x[t].x; s[1] += (double)x[t].y; s[2] += (double)x[t].z; s[3] += (double)x[t].w;
     }
   }
   __shared__ double part[kRedQ][kRedW];
-  __shared__ double red[kRedW];
+  __shared__ double red[256];
+  __shared__ double red_w[256];
 #pragma unroll
   for (int u = 0; u < 4; ++u) part[q][4 * j + u] = s[u];
   __syncthreads();
@@ -312,13 +312,29 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) a.norm_partial[blockIdx.x] = red[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0) {
+    __syncthreads();
     double ls = 0.0, ws = 0.0;
-    for (int wg = 0; wg < a.n_loss; ++wg) { ls += a.loss_partial[2 * wg]; ws += a.loss_partial[2 * wg + 1]; }
-    a.stats[0] = ls / (double)a.B;
-    a.stats[1] = ws;
-    a.stats[3] = ls;
-    *a.step_snapshot = *a.step;
+    for (int wg = (int)threadIdx.x; wg < a.n_loss; wg += 256) {
+      ls += a.loss_partial[2 * wg];
+      ws += a.loss_partial[2 * wg + 1];
+    }
+    red[threadIdx.x] = ls;
+    red_w[threadIdx.x] = ws;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+      if ((int)threadIdx.x < k) {
+        red[threadIdx.x] += red[threadIdx.x + k];
+        red_w[threadIdx.x] += red_w[threadIdx.x + k];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.stats[0] = red[0] / (double)a.B;
+      a.stats[1] = red_w[0];
+      a.stats[3] = red[0];
+      *a.step_snapshot = *a.step;
+    }
   }
 }
 
