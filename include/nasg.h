@@ -65,6 +65,9 @@ typedef struct {
                           e KL(p||q_hat) + (1-e) KL(p||q), q_hat = c q + (1-c) p_fs
                           (Sec. 4.2); hidden-64 networks only. 0: 8K outputs, NLL of q. */
   float mis_fraction;  /* e of the blended loss, in [0, 1] (the paper uses 0.2) */
+  int32_t isotropic;   /* 1: isotropic lobes, a = 0 (normalised spherical Gaussians / vMF, the
+                          comparison model of Sec. 6); the a outputs are ignored and get zero
+                          gradient. 0: NASG lobes. */
 } nasg_config;
 
 /* Device state, allocated by the caller with the sizes given below.

@@ -76,7 +76,7 @@ def euler_frame(ct, st, cp, sp, ctau, stau):
     return z, x, y
 
 
-def decode(raw, n_lobes, eps=0.0):
+def decode(raw, n_lobes, eps=0.0, isotropic=False):
     """Raw network outputs [B, 8K] (or [B, 8K + 1]) -> Lobes (Tab. "decoding",
     Sec. 4.1).
 
@@ -84,6 +84,8 @@ def decode(raw, n_lobes, eps=0.0):
     8K, when present, is the selection probability (see ``selection``).
     cos/sin values: sigmoid(s0) * 2 - 1; lambda, a: exp(s1) (after the clamp);
     mixture weights: softmax over the K logits.
+    isotropic: a = 0 for every lobe (the normalised spherical Gaussian that
+    the paper compares NASG against, Sec. 6); the a outputs are ignored.
     """
     raw = torch.as_tensor(raw, dtype=F64)
     r = raw[:, :N_PARAM * n_lobes].reshape(raw.shape[0], N_PARAM, n_lobes)
@@ -95,6 +97,8 @@ def decode(raw, n_lobes, eps=0.0):
     z, x, y = euler_frame(ct, st, cp, sp, ctau, stau)
     lam = torch.exp(torch.clamp(r[:, 5], -LOG_CLAMP, LOG_CLAMP))
     a = torch.exp(torch.clamp(r[:, 6], -LOG_CLAMP, LOG_CLAMP))
+    if isotropic:
+        a = 0.0 * a   # zero value, zero gradient
     log_A = torch.log_softmax(r[:, 7], dim=-1)
     return Lobes(z=z, x=x, y=y, lam=lam, a=a, log_A=log_A,
                  log_K=log_normaliser(lam, a, eps), eps=float(eps))

@@ -24,27 +24,27 @@ from . import mlp, nasg
 F64 = torch.float64
 
 
-def weighted_nll(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False):
+def weighted_nll(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False, isotropic=False):
     """L = mean_j w_j * (-log q(dir_j)) for one batch (scalar tensor)."""
     raw = mlp.forward(weights, feat, bf16=bf16)
-    lobes = nasg.decode(raw, n_lobes, eps)
+    lobes = nasg.decode(raw, n_lobes, eps, isotropic)
     log_q = nasg.mixture_log_pdf(dirs, lobes)
     w = torch.as_tensor(w, dtype=F64)
     return (w * (-log_q)).mean()
 
 
-def loss_and_grad(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False):
+def loss_and_grad(weights, feat, dirs, w, n_lobes, eps=0.0, bf16=False, isotropic=False):
     """(L, [dL/dW_l]) with the gradient from float64 autograd."""
     ws = [torch.as_tensor(W, dtype=F64).clone().requires_grad_(True) for W in weights]
-    L = weighted_nll(ws, feat, dirs, w, n_lobes, eps, bf16)
+    L = weighted_nll(ws, feat, dirs, w, n_lobes, eps, bf16, isotropic)
     grads = torch.autograd.grad(L, ws)
     return float(L.detach()), [g.detach() for g in grads]
 
 
-def raw_output_grad(raw, dirs, w, n_lobes, eps=0.0):
+def raw_output_grad(raw, dirs, w, n_lobes, eps=0.0, isotropic=False):
     """dL/d(raw outputs) [B, 8K] for the loss above, by autograd."""
     raw = torch.as_tensor(raw, dtype=F64).clone().requires_grad_(True)
-    log_q = nasg.mixture_log_pdf(dirs, nasg.decode(raw, n_lobes, eps))
+    log_q = nasg.mixture_log_pdf(dirs, nasg.decode(raw, n_lobes, eps, isotropic))
     w = torch.as_tensor(w, dtype=F64)
     L = (w * (-log_q)).mean()
     (g,) = torch.autograd.grad(L, raw)

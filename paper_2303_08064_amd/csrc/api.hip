@@ -60,6 +60,7 @@ const char* config_error(const nasg_config* c) {
   if (c->selection == 1 && is_large(c->hidden, c->n_lobes, c->precision))
     return "the selection output is compiled for hidden 64 networks";
   if (!(c->mis_fraction >= 0.0f && c->mis_fraction <= 1.0f)) return "mis_fraction must be in [0, 1]";
+  if (c->isotropic != 0 && c->isotropic != 1) return "isotropic must be 0 or 1";
   if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
   if (!(c->lr > 0.0f) || !isfinite(c->lr)) return "lr must be finite and > 0";
   if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
@@ -241,6 +242,7 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.raw_out = raw_out;
   a.sel_out = sel_out;
   a.sel = ctx->d.S;
+  a.amul = ctx->cfg.isotropic ? 0.0f : 1.0f;
   a.num_cus = ctx->num_cus;
   hipError_t e = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)
                      ? launch_large_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream)
@@ -365,6 +367,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   t.sel = ctx->d.S;
   t.bsdf_pdf = bsdf_pdf;
   t.mis_e = ctx->cfg.mis_fraction;
+  t.amul = ctx->cfg.isotropic ? 0.0f : 1.0f;
   hipError_t e;
   if (large) {
     LargeTrainArgs la;
@@ -379,6 +382,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.partial = t.partial;
     la.loss_partial = t.loss_partial;
     la.n_weights = t.n_weights;
+    la.amul = t.amul;
     e = launch_large_train(la, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, n_loss, (hipStream_t)stream);
   } else {
     e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);

@@ -59,7 +59,7 @@ __device__ __forceinline__ float logit_lse(const float (&out)[MTO][4]) {
 template <int KQ, int MTO, int S = 0>
 __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], float vx, float vy, float vz,
                                                 float gs, bool valid, float eps, float (&dl)[MTO][4],
-                                                float pdf_bsdf = 0.0f, float mis_e = 0.0f) {
+                                                float pdf_bsdf = 0.0f, float mis_e = 0.0f, float amul = 1.0f) {
   constexpr int TS = 2 * KQ;   // the selection tile (S = 1)
   static_assert(MTO == 2 * KQ + S, "output tiles: 8K rows plus the selection tile");
   // softmax of the K logits: A_k = e^{alpha_k - m} / sum, kept for the logit gradient
@@ -91,7 +91,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
     lobe_raw<KQ, MTO>(out, q, o);
     Lobe L;
     LobeAux X;
-    decode_lobe(o, eps, L, X);
+    decode_lobe(o, eps, L, X, amul);
     L.logc = (o[7] - lse) - X.logK;
     const Eval e = eval_lobe(L, vx, vy, vz, eps);
     ell[q] = e.ell;
@@ -150,13 +150,13 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
 template <int KQ, int MTO>
 __device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], float xi_sel, float xi0, float xi1,
                                                 float xi2, float eps, int g, int c, Lobe (&lb)[KQ], float& vx,
-                                                float& vy, float& vz) {
+                                                float& vy, float& vz, float amul = 1.0f) {
   float logK[KQ], alpha[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     float o[8];
     lobe_raw<KQ, MTO>(out, q, o);
-    logK[q] = decode_lobe_query(o, eps, lb[q]);
+    logK[q] = decode_lobe_query(o, eps, lb[q], amul);
     alpha[q] = o[7];
   }
   // mixture weights: softmax over the K logits

@@ -30,6 +30,7 @@ struct QueryArgs {
   float* raw_out;
   float* sel_out;        // selection probability c per vertex (optional)
   int sel;               // 1: the network has the selection output (8K + 1 rows)
+  float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
 };
 
@@ -60,6 +61,7 @@ struct TrainArgs {
   int sel;               // 1: selection output and the blended loss
   const float* bsdf_pdf; // [B] p_fs at each training direction (sel = 1)
   float mis_e;           // e of the blended loss (sel = 1)
+  float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
 };
 
 struct LargeTrainArgs {
@@ -74,6 +76,7 @@ struct LargeTrainArgs {
   float* partial;        // [n_wg][n_weights] (backward kernels' grid)
   double* loss_partial;  // [n_grad][2] (gradient kernel's grid)
   int64_t n_weights;
+  float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
 };
 
 struct ReduceArgs {

@@ -412,7 +412,8 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
     }
     Lobe lb[KQ];
     float vx, vy, vz;
-    const float logq = query_epilogue<KQ, N::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz);
+    const float logq =
+        query_epilogue<KQ, N::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz, a.amul);
     if (valid && g == 0) {
       a.dir_out[v] = vx;
       a.dir_out[a.ld + v] = vy;
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
     }
     const float gs = valid ? -wj * inv_b : 0.0f;
     float dl[MTO][4];
-    const float logq = train_epilogue<KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl);
+    const float logq = train_epilogue<KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl, 0.0f, 0.0f, a.amul);
     if (valid && g == 0) {
       loss_sum += (double)wj * (double)(-logq);
       w_sum += (double)wj;
@@ -571,7 +572,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
       vx *= inv; vy *= inv; vz *= inv;
       const float gs = valid ? -wj * inv_b : 0.0f;
       float dl[MTO][4];
-      const float logq = train_epilogue<N::KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl);
+      const float logq = train_epilogue<N::KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl, 0.0f, 0.0f, a.amul);
       if (valid && g == 0) {
         loss_sum += (double)wj * (double)(-logq);
         w_sum += (double)wj;

@@ -127,7 +127,10 @@ __device__ __forceinline__ void decode_pair(float oc, float os, float& cu, float
   hs = 2.0f * (1.0f - ms) * rs * rs;
 }
 
-__device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X) {
+// amul = 0 decodes isotropic lobes (a = 0: the normalised spherical
+// Gaussian / von Mises-Fisher lobe; the anisotropy output then has zero
+// gradient), 1 the NASG lobe.
+__device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X, float amul = 1.0f) {
   const float e0 = fexp(-fabsf(o[0]));
   const float r0 = frcp(1.0f + e0);
   X.ct = copysignf((1.0f - e0) * r0, o[0]);
@@ -146,7 +149,7 @@ __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L
   X.loglam = fminf(fmaxf(o[5], -kLogClamp), kLogClamp);
   X.loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
   L.lam = fexp(X.loglam);
-  L.a = fexp(X.loga);
+  L.a = amul * fexp(X.loga);
   X.logK = log_normaliser(L.lam, X.loglam, L.a, eps, X.qlam);
   L.logc = 0.0f;
 }
@@ -161,7 +164,7 @@ __device__ __forceinline__ float one_minus_exp_neg(float ao) {
 // the sin/cos pairs normalised without reciprocals (a pair of tanh(o/2) =
 // m/(2 - m) values is scaled by (2 - m1)(2 - m2) > 0 before normalising) and
 // log K folded into log c by the caller. Returns log K.
-__device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, Lobe& L) {
+__device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, Lobe& L, float amul = 1.0f) {
   // theta: cos = tanh(o0/2) (absolute accuracy suffices), sin = sech(o0/2)
   const float e0 = fexp(-fabsf(o[0]));
   const float r0 = frcp(1.0f + e0);
@@ -182,7 +185,7 @@ __device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, 
   const float loglam = fminf(fmaxf(o[5], -kLogClamp), kLogClamp);
   const float loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
   L.lam = fexp(loglam);
-  L.a = fexp(loga);
+  L.a = amul * fexp(loga);
   L.logc = 0.0f;
   return log_normaliser(L.lam, loglam, L.a, eps);
 }

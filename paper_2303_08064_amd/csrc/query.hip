@@ -62,7 +62,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
     }
     Lobe lb[KQ];
     float vx, vy, vz;
-    const float logq = query_epilogue<KQ, F::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz);
+    const float logq =
+        query_epilogue<KQ, F::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz, a.amul);
 
     if (valid && g == 0) {
       a.dir_out[v] = vx;

@@ -141,7 +141,7 @@ void train_kernel(TrainArgs a) {
     }
     const float gs = valid ? -wj * inv_b : 0.0f;   // dL/dlog q (of the log term)
     float dl[MTO][4];
-    const float lterm = train_epilogue<KQ, MTO, SEL>(out, vx, vy, vz, gs, valid, a.eps, dl, pfs, a.mis_e);
+    const float lterm = train_epilogue<KQ, MTO, SEL>(out, vx, vy, vz, gs, valid, a.eps, dl, pfs, a.mis_e, a.amul);
     if (valid && g == 0) {
       loss_sum += (double)wj * (double)(-lterm);
       w_sum += (double)wj;

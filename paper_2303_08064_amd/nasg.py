@@ -42,14 +42,15 @@ class NasgGuide:
     synth.flat_weights(synth.init_weights(...)).
     selection: the network has the selection-probability output and trains
     on the blended loss with fraction mis_fraction (Sec. 4.2).
+    isotropic: a = 0 lobes (normalised spherical Gaussians), for comparisons.
     """
 
     def __init__(self, weights, hidden=64, n_hidden=4, n_lobes=16, precision="bf16", eps=0.0,
                  lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, device="cuda",
-                 selection=False, mis_fraction=0.2):
+                 selection=False, mis_fraction=0.2, isotropic=False):
         self.lib = load()
         self.cfg = Config(hidden, n_hidden, n_lobes, PRECISIONS[precision], eps, lr, beta1, beta2,
-                          adam_eps, max_batch, int(bool(selection)), mis_fraction)
+                          adam_eps, max_batch, int(bool(selection)), mis_fraction, int(bool(isotropic)))
         self.selection = bool(selection)
         self.n_lobes = n_lobes
         self.hidden = hidden

@@ -442,3 +442,35 @@ def test_pdf_direction_gradient(name, eps):
     assert err[ok].max() < 1e-4, err[ok].max()
     assert err[~near_minus_z_].max() < 1e-2, err[~near_minus_z_].max()
     assert np.abs((gg * uni.T).sum(1)).max() < 1e-4 * (np.abs(gg).max() + 1)
+
+
+# ---- isotropic lobes (a = 0: the spherical-Gaussian comparison model) ----
+
+@pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
+def test_isotropic_query_and_gradient(name):
+    """isotropic = 1: records carry a = 0 and the pdf is the vMF mixture of
+    the oracle's isotropic decode; the loss and gradient follow it (FP32
+    stage-wise 1e-4, BF16 2e-2) and the a outputs' weights get none."""
+    K, prec = CONFIGS[name][2], CONFIGS[name][3]
+    g, mats = make_guide(name, out_scale=2.0, isotropic=True)
+    feat, xi = inputs(B_RAGGED, 27)
+    d, pdf, rec = g.query(to_dev(feat), to_dev(xi), records=True)
+    recg = rec_to_bk9(rec, B_RAGGED, K)
+    assert np.all(recg[..., 7] == 0.0)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    lob = onasg.decode(torch.tensor(raw), K, isotropic=True)
+    dd = d.cpu().numpy().T.astype(np.float64)
+    lq = onasg.mixture_log_pdf(torch.tensor(dd), lob).numpy()
+    assert np.abs(np.log(pdf.cpu().numpy()) - lq).max() < 1e-4
+    tf, td, tw = _train_batch(B_RAGGED, 28)
+    g.loss_grad(to_dev(tf), to_dev(td), to_dev(tw))
+    torch.cuda.synchronize()
+    W = w64(mats)
+    traw = g.forward_raw(to_dev(tf)).cpu().numpy().T.astype(np.float64)
+    g_raw = otrain.raw_output_grad(traw, td.T, tw.astype(np.float64), K, isotropic=True)
+    staged = otrain.weight_grad_from_raw_grad(W, tf.T, g_raw, bf16=prec == "bf16")
+    gg = g.split(g.grad.cpu())
+    errs = _rel_errors(gg, staged)
+    assert max(errs) < (1e-4 if prec == "f32" else 2e-2), errs
+    a_rows = [6 * K + k for k in range(K)]   # canonical rows of the log a outputs
+    assert float(torch.abs(gg[-1][a_rows]).max()) == 0.0

@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(lib):
 def _cfg(**kw):
     from paper_2303_08064_amd._lib import Config
     base = dict(hidden=64, n_hidden=4, n_lobes=16, precision=1, eps=0.0, lr=1e-3, beta1=0.9,
-                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, selection=0, mis_fraction=0.2)
+                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, selection=0, mis_fraction=0.2, isotropic=0)
     base.update(kw)
     return Config(**base)
 

@@ -601,3 +601,21 @@ def test_direction_gradient_matches_finite_differences():
             fd = (fp - fm) / (2 * h)
             err = np.abs(fd - (g * t).sum(1))
             assert err.max() < 1e-6 * max(1.0, np.abs(g).max()), (eps, err.max())
+
+
+def test_isotropic_decode_is_vmf_mixture():
+    """isotropic = True: a = 0 for every lobe and the mixture equals scipy's
+    von Mises-Fisher mixture with kappa = lambda and the softmax weights."""
+    rng = np.random.default_rng(51)
+    K, B = 3, 16
+    raw = torch.tensor(rng.standard_normal((B, 8 * K)))
+    lob = nasg.decode(raw, K, isotropic=True)
+    assert float(torch.abs(lob.a).max()) == 0.0
+    d = rng.standard_normal((B, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    lq = nasg.mixture_log_pdf(torch.tensor(d), lob).numpy()
+    A = np.exp(lob.log_A.numpy())
+    ref = np.zeros(B)
+    for b in range(B):
+        ref[b] = np.log(sum(A[b, k] * np.exp(ss.vonmises_fisher(mu=lob.z[b, k].numpy(), kappa=float(lob.lam[b, k])).logpdf(d[b]))
+                            for k in range(K)))
+    assert np.abs(lq - ref).max() < 1e-9
