@@ -9,6 +9,8 @@ What it computes, in plain float64 PyTorch CPU ops:
 
 * ``mlp``   -- the bias-free MLP of Sec. 4.1 (input padded with a constant one
                as the bias surrogate), with an optional BF16-emulation mode.
+* ``encoding`` -- the encoded input of Tab. "encoding": one-blob bins of the
+               position, then omega_o and n.
 * ``nasg``  -- output decoding (Tab. "decoding", Euler frame of Sec. 4.1), the
                NASG lobe exactly as printed (eq. NASG; App. A with epsilon),
                its closed-form normaliser (eq. "K for NASG", App. B), the
@@ -19,6 +21,9 @@ What it computes, in plain float64 PyTorch CPU ops:
 
 Readings of the paper where it is silent (each repeated where it is used):
 
+* the one-blob encoding (Tab. "encoding") gives each position coordinate 19
+  bins (57 = 3 x 19); bin i holds a Gaussian of standard deviation 1/19
+  centred at the coordinate, evaluated at the bin centre (i + 1/2)/19;
 * raw output order is parameter-major, lobe-minor: for lobe k and parameter p
   the raw value is ``o[p*K + k]`` with p = 0..7 meaning
   (cos theta, sin phi, cos phi, sin tau, cos tau, log lambda, log a, logit);
@@ -44,4 +49,4 @@ are not fixed by the paper; the distributional pins in the test suite hold
 independently of them.
 """
 
-from . import mlp, nasg, train  # noqa: F401
+from . import encoding, mlp, nasg, train  # noqa: F401

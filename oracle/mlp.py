@@ -2,8 +2,11 @@
 
 Test infrastructure only. Sec. 4.1: fully connected layers without bias and
 ReLU between them; the input is padded with a constant one, which stands in
-for the bias (footnote of Sec. 4.1). Here the input is the 9 raw features
-(position, outgoing direction, normal) followed by that one: 10 values.
+for the bias (footnote of Sec. 4.1). The input is either the 9 raw features
+(position, outgoing direction, normal) followed by that one (10 values), or
+the paper's encoded input of Tab. "encoding" (``encoding.encode``: 63
+values) followed by that one (64 values). Which one is fixed by W_0's
+column count.
 
 Weights are a list of matrices W_l of shape [out_l, in_l]; layer l computes
 h_l = relu(W_l h_{l-1}) and the last layer is linear.
@@ -11,15 +14,22 @@ h_l = relu(W_l h_{l-1}) and the last layer is linear.
 
 import torch
 
+from . import encoding as enc
+
 F64 = torch.float64
 IN_FEATURES = 9
 
 
-def layer_shapes(hidden, n_hidden, n_lobes, selection=False):
+def input_width(encoded=False):
+    """Columns of W_0: the features plus the constant one."""
+    return (enc.ENCODED if encoded else IN_FEATURES) + 1
+
+
+def layer_shapes(hidden, n_hidden, n_lobes, selection=False, encoded=False):
     """[(out, in)] for n_hidden hidden layers of width `hidden` and 8K outputs,
     plus one for the selection probability (Sec. 4.1: d = 8N + 1) when
-    `selection` is set."""
-    shapes = [(hidden, IN_FEATURES + 1)]
+    `selection` is set; W_0 reads the encoded input when `encoded` is set."""
+    shapes = [(hidden, input_width(encoded))]
     shapes += [(hidden, hidden)] * (n_hidden - 1)
     shapes.append((8 * n_lobes + (1 if selection else 0), hidden))
     return shapes
@@ -50,17 +60,28 @@ def round_bf16(t):
     return t + (r - t.detach())
 
 
+def network_input(feat, in_cols):
+    """The input of W_0 for raw features [B, 9]: the features, or their
+    encoding when W_0 has 64 columns, followed by the constant one."""
+    feat = torch.as_tensor(feat, dtype=F64)
+    if in_cols == input_width(True):
+        feat = enc.encode(feat)
+    elif in_cols != input_width(False):
+        raise ValueError(f"W_0 has {in_cols} columns; expected {input_width(False)} or {input_width(True)}")
+    return torch.cat([feat, torch.ones(feat.shape[0], 1, dtype=F64)], dim=-1)
+
+
 def forward(weights, feat, bf16=False, return_pre=False):
-    """Raw outputs [B, 8K] for features [B, 9].
+    """Raw outputs [B, 8K (+1)] for raw features [B, 9].
 
     bf16=True emulates a BF16 GEMM with wide accumulation: every weight and
-    every layer input (the features and the constant one included) is rounded
+    every layer input (the features or their encoding, and the constant one)
+    is rounded
     to bfloat16, products are summed in float64, and a hidden pre-activation
     is rounded to float32 before the ReLU and the next rounding to bfloat16.
     The last layer's result is not rounded.
     """
-    feat = torch.as_tensor(feat, dtype=F64)
-    h = torch.cat([feat, torch.ones(feat.shape[0], 1, dtype=F64)], dim=-1)
+    h = network_input(feat, torch.as_tensor(weights[0]).shape[1])
     pre = []
     n = len(weights)
     for l, W in enumerate(weights):

@@ -1,0 +1,135 @@
+"""Pins of the oracle's encoded network input (Sec. 4.1, Tab. "encoding").
+
+Independent facts, not the formula retyped: a Gaussian sampled at unit
+spacing (in units of its standard deviation) sums to sqrt(2 pi) with its
+centroid at the centre and its variance sigma^2 (Poisson summation, with
+corrections bounded through exp(-2 pi^2) ~ 2.7e-9), the bins mirror under
+s -> 1 - s, and the largest bin is the one that contains s.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import encoding, mlp
+
+F64 = torch.float64
+K = encoding.BINS
+
+
+def _interior(n=41, seed=0):
+    # more than 6 standard deviations (6/19) from both ends of [0, 1]
+    rng = np.random.default_rng(seed)
+    return torch.tensor(rng.uniform(6.6 / K, 1.0 - 6.6 / K, n), dtype=F64)
+
+
+def test_one_blob_sums_to_gaussian_integral():
+    s = _interior()
+    v = encoding.one_blob(s)
+    assert v.shape == (s.numel(), K)
+    # sum_i exp(-(i + 1/2 - K s)^2 / 2) = sqrt(2 pi) (1 + r), |r| <= 2 e^{-2 pi^2}
+    assert torch.allclose(v.sum(-1), torch.full_like(s, math.sqrt(2 * math.pi)),
+                          rtol=1.05 * 2 * math.exp(-2 * math.pi ** 2), atol=0)
+
+
+def test_one_blob_centroid_and_width():
+    s = _interior(seed=1)
+    v = encoding.one_blob(s)
+    c = (torch.arange(K, dtype=F64) + 0.5) / K
+    w = v / v.sum(-1, keepdim=True)
+    mean = (w * c).sum(-1)
+    var = (w * (c - s[:, None]) ** 2).sum(-1)
+    # Poisson-summation bounds: 4 pi e^{-2 pi^2} / K for the mean and
+    # 2 (4 pi^2 - 1) e^{-2 pi^2} relative for the variance
+    corr = math.exp(-2 * math.pi ** 2)
+    assert torch.allclose(mean, s, rtol=0, atol=1.05 * 4 * math.pi * corr / K)
+    # standard deviation 1/K: the width of one bin
+    assert torch.allclose(var, torch.full_like(s, 1.0 / K ** 2), rtol=1.05 * 2 * (4 * math.pi ** 2 - 1) * corr,
+                          atol=0)
+
+
+def test_one_blob_mirror_and_peak_bin():
+    rng = np.random.default_rng(2)
+    s = torch.tensor(rng.uniform(0, 1, 200), dtype=F64)
+    v = encoding.one_blob(s)
+    assert torch.allclose(encoding.one_blob(1.0 - s), v.flip(-1), rtol=0, atol=1e-12)
+    # the bin that contains s holds the largest value
+    assert torch.equal(v.argmax(-1), torch.floor(s * K).long())
+    # at a bin centre the kernel is 1 there and exp(-1/2), exp(-2) one and two bins away
+    i = 7
+    vc = encoding.one_blob(torch.tensor([(i + 0.5) / K], dtype=F64))[0]
+    assert torch.allclose(vc[i - 2:i + 3], torch.tensor([math.exp(-2), math.exp(-0.5), 1.0,
+                                                         math.exp(-0.5), math.exp(-2)], dtype=F64),
+                          rtol=1e-14, atol=0)
+
+
+def test_encoded_feature_layout():
+    rng = np.random.default_rng(3)
+    feat = torch.tensor(rng.uniform(0.1, 0.9, (5, 9)), dtype=F64)
+    e = encoding.encode(feat)
+    assert e.shape == (5, encoding.ENCODED) and encoding.ENCODED == 63
+    # omega_o and n pass through unchanged after the 57 position bins
+    assert torch.equal(e[:, 57:63], feat[:, 3:9])
+    # each position coordinate moves only its own 19 bins
+    for i in range(3):
+        f2 = feat.clone()
+        f2[:, i] += 0.05
+        changed = (encoding.encode(f2) != e).any(0).nonzero().flatten().tolist()
+        assert changed == list(range(19 * i, 19 * i + 19))
+    for i in range(3, 9):
+        f2 = feat.clone()
+        f2[:, i] += 0.05
+        changed = (encoding.encode(f2) != e).any(0).nonzero().flatten().tolist()
+        assert changed == [57 + i - 3]
+
+
+def test_encoded_network_reads_bins_directions_and_one():
+    """A one-hidden-layer net whose W_0 rows pick single input columns: the
+    constant one is column 63, omega_o_x column 57, n_z column 62, and the bin
+    of a position at a bin centre reads 1."""
+    shapes = mlp.layer_shapes(8, 1, 1, encoded=True)
+    assert shapes == [(8, 64), (8, 8)]
+    W0 = torch.zeros(8, 64, dtype=F64)
+    cols = [63, 57, 62, 19 + 4, 38 + 11]
+    for r, col in enumerate(cols):
+        W0[r, col] = 1.0
+    W1 = torch.eye(8, dtype=F64)
+    feat = torch.tensor([[0.3, (4 + 0.5) / K, (11 + 0.5) / K, 0.6, -0.2, 0.75, 0.1, 0.4, 0.9]], dtype=F64)
+    out = mlp.forward([W0, W1], feat)[0]
+    assert torch.allclose(out[:5], torch.tensor([1.0, 0.6, 0.9, 1.0, 1.0], dtype=F64), rtol=1e-14, atol=0)
+    assert torch.equal(out[5:], torch.zeros(3, dtype=F64))
+    feat2 = feat.clone()
+    feat2[0, 3] = -0.6   # ReLU of a negative direction component
+    assert float(mlp.forward([W0, W1], feat2)[0, 1]) == 0.0
+    with pytest.raises(ValueError):
+        mlp.forward([torch.zeros(8, 12, dtype=F64), W1], feat)
+
+
+def test_encoded_selection_net_gradient_matches_finite_differences():
+    """The paper's network shape in miniature (encoded input, selection
+    output, blended loss of Sec. 4.2): autograd against central differences
+    for W_0's columns of bins, directions and the constant one, and every
+    entry of the later layers."""
+    from oracle import train
+    rng = np.random.default_rng(41)
+    K = 2
+    shapes = mlp.layer_shapes(8, 2, K, selection=True, encoded=True)
+    Ws = [torch.tensor(rng.uniform(-0.5, 0.5, s)) for s in shapes]
+    B = 5
+    feat = torch.tensor(np.concatenate([rng.uniform(0, 1, (B, 3)), rng.standard_normal((B, 6))], 1))
+    d = rng.standard_normal((B, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    dirs, w = torch.tensor(d), torch.tensor(np.exp(rng.standard_normal(B)))
+    pdf = torch.tensor(np.exp(rng.uniform(-2, 1, B)))
+    L, g = train.blended_loss_and_grad(Ws, feat, dirs, w, pdf, K, e=0.2)
+    cols0 = [0, 5, 18, 23, 40, 56, 57, 60, 62, 63]
+    for l, W in enumerate(Ws):
+        idx = [(r, c) for r in range(W.shape[0]) for c in (cols0 if l == 0 else range(W.shape[1]))]
+        for (r, c) in idx:
+            h = 1e-6 * max(1.0, abs(float(W[r, c])))
+            wp = [x.clone() for x in Ws]; wp[l][r, c] += h
+            wm = [x.clone() for x in Ws]; wm[l][r, c] -= h
+            fd = (train.blended_nll(wp, feat, dirs, w, pdf, K, 0.2)
+                  - train.blended_nll(wm, feat, dirs, w, pdf, K, 0.2)) / (2 * h)
+            assert abs(float(fd) - float(g[l][r, c])) < 1e-6 * max(1.0, float(g[l].abs().max())), (l, r, c)
