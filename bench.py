@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-configs", action="store_true")
-    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy", "c5"], default=None,
+    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy", "c5", "paper"], default=None,
                    help="run one leg only (for profilers)")
     return p.parse_args()
 
@@ -97,6 +97,76 @@ class Frame:
         for (f, xi), (d, p) in zip(self.q_in, self.q_out):
             g.query(f, xi, dir_out=d, pdf_out=p)
         g.train_step(*self.t_in)
+
+
+# The paper's default configuration (Sec. 4.1, Sec. 6): 4 hidden layers of
+# 128 units on the encoded input, K = 8 lobes plus the selection output, and
+# S = 2^16 training samples per frame taken as T = 16 steps of t = 4096 (Sec. 5)
+PAPER_T, PAPER_TB = 16, 4096
+
+
+class PaperFrame:
+    """One frame of the paper's default configuration: the same four bounces
+    of queries, then T Adam steps of t samples each on the blended loss."""
+
+    def __init__(self, seed=3000):
+        import torch
+        from paper_2303_08064_amd import synth
+        from paper_2303_08064_amd.nasg import NasgGuide
+        self.torch = torch
+        mats = synth.init_weights(synth.layer_shapes(128, 4, 8, selection=True, encoded=True), synth.rng_for(42))
+        self.guide = NasgGuide(synth.flat_weights(mats), hidden=128, n_hidden=4, n_lobes=8, precision="bf16",
+                               lr=1e-3, max_batch=PAPER_TB, selection=True, mis_fraction=0.2, encoded=True)
+        rng = synth.rng_for(seed)
+        dev = "cuda"
+        self.q_in = [(torch.from_numpy(synth.features(n, rng)).to(dev),
+                      torch.from_numpy(synth.uniforms(n, rng)).to(dev)) for n in BOUNCES]
+        self.q_out = [(torch.empty(3, n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev))
+                      for n in BOUNCES]
+        tgt = synth.VmfTarget(4, seed=1001)
+        self.t_in = []
+        for _ in range(PAPER_T):
+            f, d, w = synth.training_batch(PAPER_TB, rng, tgt)
+            pdf = synth.lambert_pdf(d, f[6:9])
+            self.t_in.append(tuple(torch.from_numpy(x).to(dev) for x in (f, d, w, pdf)))
+        torch.cuda.synchronize()
+
+    def run(self):
+        g = self.guide
+        for (f, xi), (d, p, c) in zip(self.q_in, self.q_out):
+            g.query(f, xi, dir_out=d, pdf_out=p, sel_out=c)
+        for f, d, w, pdf in self.t_in:
+            g.train_step(f, d, w, bsdf_pdf=pdf)
+
+
+def paper_leg(steps, use_graph):
+    """The paper's default configuration, timed like the main frame, plus
+    its query and single training step on their own."""
+    fr = PaperFrame()
+    ms, _ = time_frames(fr, steps, 2, use_graph)
+    g = fr.guide
+    (f, xi), (d, p, c) = fr.q_in[0], fr.q_out[0]
+    ms_q = kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p, sel_out=c), 10)
+    f0, d0, w0, p0 = fr.t_in[0]
+    ms_t = kernel_avg_ms(lambda: g.train_step(f0, d0, w0, bsdf_pdf=p0), 20)
+    nq = sum(BOUNCES)
+    ns = PAPER_T * PAPER_TB
+    q_fl = mlp_flops_net(128, 4, 8, 64, 1)
+    return {
+        "workload": "paper default: encoded input (one-blob 57 + omega_o + n + 1 = 64) -> 128x4 -> 8*8+1 "
+                    "(K=8 with selection), BF16; queries 2^20+600000+300000+120000 and 16 Adam steps of "
+                    "4096 samples (S = 2^16, blended loss) per frame, HIP graph replay",
+        "ms_per_frame": round(ms, 4), "queries_per_s": round(nq / (ms * 1e-3), 1),
+        "train_samples_per_s": round(ns / (ms * 1e-3), 1),
+        "query_2e20_ms": round(ms_q, 4), "query_mfma_tflops": round(q_fl * (1 << 20) / (ms_q * 1e-3) / 1e12, 1),
+        "train_step_4096_us": round(ms_t * 1e3, 1),
+    }
+
+
+def mlp_flops_net(hidden, n_hidden, k, n_in, sel):
+    """Forward MFMA FLOPs of one vertex: n_in inputs (with the one), n_hidden
+    layers of `hidden`, 8k + sel outputs."""
+    return 2 * (hidden * n_in + (n_hidden - 1) * hidden * hidden + (8 * k + sel) * hidden)
 
 
 def time_frames(frame, steps, warmup, use_graph):
@@ -392,6 +462,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "c5", "steps": a.steps}))
         return
+    if a.only == "paper":
+        print(json.dumps({"only": "paper", **paper_leg(a.steps, not a.no_graph)}))
+        return
     if a.only == "records":
         print(json.dumps({"only": "records", **records_legs(frame, a.steps)}))
         return
@@ -423,6 +496,7 @@ def main():
         out["train_step"] = train_leg(frame)
     if not a.no_configs and a.only != "frame":
         out["configs"] = config_legs()
+        out["configs"]["paper_default_frame"] = paper_leg(10, not a.no_graph)
     if not a.no_fp32 and a.only != "frame":
         f32 = Frame("f32")
         ms32, _ = time_frames(f32, max(5, a.steps // 5), 2, not a.no_graph)

@@ -48,12 +48,18 @@ enum { NASG_F32 = 0, NASG_BF16 = 1 };
 
 /* Network and optimiser configuration.
  * Layers: W_0 is [hidden][10] (9 features + the constant-one input that
- * stands in for the bias, footnote of Sec. 4.1), then n_hidden-1 matrices
- * [hidden][hidden], then the output W_L [8*n_lobes + selection][hidden]. ReLU
- * between layers, none after the last (Sec. 4.1). */
+ * stands in for the bias, footnote of Sec. 4.1), or [hidden][64] with the
+ * encoded input (see `encoding`), then n_hidden-1 matrices [hidden][hidden],
+ * then the output W_L [8*n_lobes + selection][hidden]. ReLU between layers,
+ * none after the last (Sec. 4.1).
+ * Compiled networks: hidden 64 with n_lobes 4, 8 or 16 (raw features, with or
+ * without the selection output); hidden 128 with n_lobes 32 (raw features, no
+ * selection output); each in FP32 or BF16; and the paper's default network
+ * (Sec. 4.1, Sec. 6): hidden 128, n_lobes 8, the selection output and the
+ * encoded input, in BF16. Hidden-128 networks have n_hidden = 4. */
 typedef struct {
-  int32_t hidden;      /* 64 or 128 */
-  int32_t n_hidden;    /* number of hidden layers, 1..8 */
+  int32_t hidden;      /* 64 or 128 (see the compiled networks above) */
+  int32_t n_hidden;    /* number of hidden layers, 1..4 */
   int32_t n_lobes;     /* K: 4, 8, 16 or 32 */
   int32_t precision;   /* NASG_F32: FP32 MFMA; NASG_BF16: BF16 operands, FP32
                           accumulation. NASG math is FP32 in both. */
@@ -68,6 +74,12 @@ typedef struct {
   int32_t isotropic;   /* 1: isotropic lobes, a = 0 (normalised spherical Gaussians / vMF, the
                           comparison model of Sec. 6); the a outputs are ignored and get zero
                           gradient. 0: NASG lobes. */
+  int32_t encoding;    /* 1: W_0 reads the encoded input of Tab. "encoding", computed on the device
+                          from the same 9 raw features: 19 one-blob bins per position coordinate
+                          (bin b of coordinate s holds exp(-(19 s - b - 1/2)^2 / 2), a Gaussian of
+                          standard deviation 1/19 at the bin centre; s is the position in the
+                          scene's bounding box, [0, 1]), then omega_o, n and the constant one: 64
+                          inputs. 0: the 9 raw features and the one. */
 } nasg_config;
 
 /* Device state, allocated by the caller with the sizes given below.

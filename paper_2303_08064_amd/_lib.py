@@ -28,7 +28,7 @@ class Config(ctypes.Structure):
         ("precision", ctypes.c_int32), ("eps", ctypes.c_float), ("lr", ctypes.c_float),
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
         ("max_batch", ctypes.c_int64), ("selection", ctypes.c_int32), ("mis_fraction", ctypes.c_float),
-        ("isotropic", ctypes.c_int32),
+        ("isotropic", ctypes.c_int32), ("encoding", ctypes.c_int32),
     ]
 
 

@@ -30,35 +30,44 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool compiled(int H, int K, int prec) {
-#define NASG_CASE(h, k, p) if (H == h && K == k && prec == p) return true;
+// hidden-64 networks: any (K, precision) of the list, with or without the
+// selection output, on the raw features
+bool small_compiled(const nasg_config* c) {
+#define NASG_CASE(h, k, p) \
+  if (c->hidden == h && c->n_lobes == k && c->precision == p && c->encoding == 0) return true;
   NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+  return false;
+}
+
+// hidden-128 networks: exactly the listed variants
+bool large_compiled(const nasg_config* c) {
+#define NASG_CASE(h, k, p, s, e)                                                                     \
+  if (c->hidden == h && c->n_lobes == k && c->precision == p && c->selection == s && c->encoding == e) \
+    return true;
   NASG_FOR_EACH_LARGE_NET(NASG_CASE)
 #undef NASG_CASE
   return false;
 }
 
-bool is_large(int H, int K, int prec) {
-#define NASG_CASE(h, k, p) if (H == h && K == k && prec == p) return true;
-  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
-#undef NASG_CASE
-  return false;
-}
+bool is_large(const nasg_config* c) { return c->hidden == 128; }
 
-NetDims dims_of(const nasg_config* c) { return NetDims{c->hidden, c->n_hidden, c->n_lobes, c->selection}; }
+NetDims dims_of(const nasg_config* c) {
+  return NetDims{c->hidden, c->n_hidden, c->n_lobes, c->selection, c->encoding};
+}
 
 const char* config_error(const nasg_config* c) {
   if (c == nullptr) return "config is NULL";
   if (c->n_hidden < 1 || c->n_hidden > 4) return "n_hidden must be in 1..4";
   if (c->precision != NASG_F32 && c->precision != NASG_BF16) return "precision must be NASG_F32 or NASG_BF16";
-  if (!compiled(c->hidden, c->n_lobes, c->precision))
-    return "unsupported (hidden, n_lobes); compiled: hidden 64 with n_lobes 4, 8, 16 and hidden 128 with "
-           "n_lobes 32, each in FP32 or BF16";
-  if (is_large(c->hidden, c->n_lobes, c->precision) && c->n_hidden != 4)
-    return "hidden 128 networks are compiled for n_hidden = 4";
   if (c->selection != 0 && c->selection != 1) return "selection must be 0 or 1";
-  if (c->selection == 1 && is_large(c->hidden, c->n_lobes, c->precision))
-    return "the selection output is compiled for hidden 64 networks";
+  if (c->encoding != 0 && c->encoding != 1) return "encoding must be 0 or 1";
+  if (!(is_large(c) ? large_compiled(c) : small_compiled(c)))
+    return "unsupported network; compiled: hidden 64 with n_lobes 4, 8 or 16 on the raw features, with or "
+           "without the selection output; hidden 128 with n_lobes 32 on the raw features without it; each in "
+           "FP32 or BF16; and the paper's network, hidden 128 with n_lobes 8, the selection output and the "
+           "encoded input, in BF16";
+  if (is_large(c) && c->n_hidden != 4) return "hidden 128 networks are compiled for n_hidden = 4";
   if (!(c->mis_fraction >= 0.0f && c->mis_fraction <= 1.0f)) return "mis_fraction must be in [0, 1]";
   if (c->isotropic != 0 && c->isotropic != 1) return "isotropic must be 0 or 1";
   if (!(c->eps >= 0.0f) || !isfinite(c->eps)) return "eps must be finite and >= 0";
@@ -88,12 +97,9 @@ Workspace carve(const nasg_config* c) {
   w.step_snapshot = off;
   off = align_up(off + sizeof(int64_t));
   w.dout = off;
-  if (is_large(c->hidden, c->n_lobes, c->precision)) {
-    // dL/d(raw outputs) of every sample of a training batch (64-vertex tiles),
-    // BF16 or FP32 as the network
-    const int64_t tiles = (c->max_batch + 63) / 64;
-    const size_t elem = c->precision == NASG_BF16 ? 2 : 4;
-    off = align_up(off + (size_t)tiles * 64 * 8 * c->n_lobes * elem);
+  if (is_large(c)) {
+    // dL/d(raw outputs) of every sample of a training batch, BF16 or FP32 as the network
+    off = align_up(off + large_dout_bytes(c->max_batch, c->n_lobes, c->selection, c->precision));
   }
   w.total = off;
   return w;
@@ -170,8 +176,7 @@ nasg_status nasg_create(const nasg_config* cfg, const nasg_state* st, nasg_ctx**
   c->d = dims_of(cfg);
   c->ws = carve(cfg);
   c->num_cus = cus > 0 ? cus : 1;
-  e = launch_pack(st->w, st->wpack, cfg->hidden, cfg->n_hidden, cfg->n_lobes, cfg->selection, cfg->precision,
-                  nullptr);
+  e = launch_pack(st->w, st->wpack, c->d, cfg->precision, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     delete c;
@@ -185,8 +190,7 @@ void nasg_destroy(nasg_ctx* ctx) { delete ctx; }
 
 nasg_status nasg_pack(nasg_ctx* ctx, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_pack", "ctx is NULL");
-  hipError_t e = launch_pack(ctx->st.w, ctx->st.wpack, ctx->d.H, ctx->d.NH, ctx->d.K, ctx->d.S,
-                             ctx->cfg.precision, (hipStream_t)stream);
+  hipError_t e = launch_pack(ctx->st.w, ctx->st.wpack, ctx->d, ctx->cfg.precision, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail("nasg_pack", e);
 }
 
@@ -244,8 +248,8 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.sel = ctx->d.S;
   a.amul = ctx->cfg.isotropic ? 0.0f : 1.0f;
   a.num_cus = ctx->num_cus;
-  hipError_t e = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision)
-                     ? launch_large_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream)
+  hipError_t e = is_large(&ctx->cfg)
+                     ? launch_large_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream)
                      : launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
@@ -324,6 +328,7 @@ static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
   a.NH = ctx->d.NH;
   a.K = ctx->d.K;
   a.S = ctx->d.S;
+  a.E = ctx->d.E;
   a.prec = ctx->cfg.precision;
   a.lr = ctx->cfg.lr;
   a.beta1 = ctx->cfg.beta1;
@@ -347,8 +352,9 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   else if (bsdf_pdf != nullptr) return fail(NASG_E_ARG, fn, "bsdf_pdf needs a network with the selection output");
   const nasg_state& s = ctx->st;
   unsigned char* ws = static_cast<unsigned char*>(s.workspace);
-  const int n_wg = train_workgroups(B, ctx->num_cus);
-  const bool large = is_large(ctx->d.H, ctx->d.K, ctx->cfg.precision);
+  const bool large = is_large(&ctx->cfg);
+  const int n_wg = large ? large_train_workgroups(B, ctx->num_cus, ctx->cfg.precision)
+                         : train_workgroups(B, ctx->num_cus);
   const int n_loss = large ? large_loss_workgroups(B, ctx->num_cus, ctx->cfg.precision) : n_wg;
   TrainArgs t;
   t.wpack = s.wpack;
@@ -376,6 +382,8 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.feat = feat;
     la.dir = dir;
     la.w = w;
+    la.bsdf_pdf = bsdf_pdf;
+    la.mis_e = ctx->cfg.mis_fraction;
     la.ld = ld;
     la.B = B;
     la.dout = ws + ctx->ws.dout;
@@ -383,7 +391,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.loss_partial = t.loss_partial;
     la.n_weights = t.n_weights;
     la.amul = t.amul;
-    e = launch_large_train(la, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, n_loss, (hipStream_t)stream);
+    e = launch_large_train(la, ctx->d, ctx->cfg.precision, n_wg, n_loss, (hipStream_t)stream);
   } else {
     e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);
   }

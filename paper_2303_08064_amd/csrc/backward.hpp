@@ -226,7 +226,7 @@ __device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l
       for (int i = 0; i < 4; ++i) {
         const int R = rt[r] * 16 + 4 * g + i;
         const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-        part[off + (int64_t)n * cols + k] = acc[r][ct][i];
+        if (n >= 0) part[off + (int64_t)n * cols + k] = acc[r][ct][i];   // n < 0: padding rows
       }
     }
   }

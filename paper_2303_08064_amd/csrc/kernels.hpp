@@ -11,8 +11,10 @@
   X(64, 4, 0) X(64, 4, 1) X(64, 8, 0) X(64, 8, 1) X(64, 16, 0) X(64, 16, 1)
 // Large networks (4 hidden layers): weights stream through LDS while the
 // workgroup moves through the layers, and training runs as separate
-// NASG-gradient and backward kernels.
-#define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0) X(128, 32, 1)
+// NASG-gradient and backward kernels. (hidden, lobes, precision, selection
+// output, encoded input): K = 32 on the raw features, and the paper's default
+// network (Sec. 4.1, Sec. 6).
+#define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0) X(128, 8, 1, 1, 1)
 
 namespace nasg {
 
@@ -70,9 +72,11 @@ struct LargeTrainArgs {
   const float* feat;
   const float* dir;
   const float* w;
+  const float* bsdf_pdf; // [B] p_fs at each training direction (selection output)
+  float mis_e;           // e of the blended loss (selection output)
   int64_t ld, B;
-  void* dout;            // dL/d(raw outputs) per 16 vertices: BF16 operand image (16 B x K/4 x 64)
-                         // or FP32 accumulator image (16 B x K/2 x 64)
+  void* dout;            // dL/d(raw outputs) per 16 vertices: BF16 operand image (16 B x K/4 x 64,
+                         // then 8 B x 64 for the selection tile) or FP32 accumulator image (16 B x K/2 x 64)
   float* partial;        // [n_wg][n_weights] (backward kernels' grid)
   double* loss_partial;  // [n_grad][2] (gradient kernel's grid)
   int64_t n_weights;
@@ -106,7 +110,7 @@ struct AdamArgs {
   const double* norm_partial;
   int n_norm;
   int64_t n_weights;
-  int H, NH, K, S, prec;
+  int H, NH, K, S, E, prec;
   float lr, beta1, beta2, adam_eps;
 };
 
@@ -178,20 +182,23 @@ hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_pdf_grad(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hipStream_t st);
-hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, int n_grad,
+hipError_t launch_large_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st);
+hipError_t launch_large_train(const LargeTrainArgs& a, const NetDims& d, int prec, int n_wg, int n_grad,
                               hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
-hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int S, int prec, hipStream_t st);
+hipError_t launch_pack(const float* w, void* wpack, const NetDims& d, int prec, hipStream_t st);
 hipError_t launch_fill(void* p, int64_t n_words, uint32_t value, hipStream_t st);
 
 // Query / train kernel grid bounds (workgroups) for a batch of B vertices.
 constexpr int kMaxTrainWG = 256;
 int train_workgroups(int64_t B, int num_cus);
-// loss partials the large network's training writes (the workgroups of the
-// kernel that evaluates the loss)
+// the large network's training: its backward kernels' grid, the loss
+// partials it writes (the workgroups of the kernel that evaluates the loss),
+// and the bytes of its raw-output gradient images for up to B vertices
+int large_train_workgroups(int64_t B, int num_cus, int prec);
 int large_loss_workgroups(int64_t B, int num_cus, int prec);
+size_t large_dout_bytes(int64_t B, int K, int S, int prec);
 int reduce_blocks(int64_t n_weights);
 
 }  // namespace nasg

@@ -1,11 +1,14 @@
-// Large networks (hidden 128, K = 32): query and training, BF16 and FP32.
+// Hidden-128 networks (four hidden layers): query and training. Compiled:
+// K = 32 lobes on the 9 raw features, BF16 and FP32; and the paper's default
+// network (Sec. 4.1, Sec. 6: 128 units, K = 8, the selection output, the
+// encoded input of Tab. "encoding"), BF16.
 //
-// This network's forward weights alone (164 KiB in BF16) exceed one CU's
-// 160 KiB of LDS, and its 83,200 FP32 weight-gradient accumulators would need
-// ~325 registers per lane in each of four waves. So:
+// The K = 32 network's forward weights alone (164 KiB in BF16) exceed one
+// CU's 160 KiB of LDS, and its 83,200 FP32 weight-gradient accumulators would
+// need ~325 registers per lane in each of four waves. So:
 // * weights stream through LDS while the workgroup moves through the layers
 //   together (64 vertices per tile). BF16: two 32 KiB buffers in a pipeline;
-//   each stage is one layer of MFMA fragments (the output layer in two
+//   each stage is one layer of MFMA fragments (a K = 32 output layer in two
 //   halves), and while the waves compute from one buffer the next stage
 //   arrives in the other by asynchronous direct-to-LDS loads. FP32 (the
 //   comparison path): one buffer, 64 rows (33 KiB) at a time.
@@ -42,6 +45,13 @@ struct Pk {
       const u32x4 w = __builtin_bit_cast(u32x4, b[kb]);
       p[2 * kb][0] = w[0]; p[2 * kb][1] = w[1]; p[2 * kb + 1][0] = w[2]; p[2 * kb + 1][1] = w[3];
     }
+  }
+  // the selection tile (an odd last tile) from its 16x16x16 B operand
+  __device__ void set_last(const bf16x4& b) {
+    typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
+    const u32x2 w = __builtin_bit_cast(u32x2, b);
+    p[RT - 1][0] = w[0];
+    p[RT - 1][1] = w[1];
   }
   __device__ void ops(bf16x8 (&b)[RT / 2]) const {
 #pragma unroll
@@ -80,40 +90,88 @@ struct Pk {
   }
 };
 
-// Stage order of one tile's forward: layer 0, hidden layers 1..NH-1, output
-// rows [0, 4K) and [4K, 8K); stage s computes from buffer s % 2 while stage
-// s + 1 is copied into the other. With NH even the stage after the forward
-// (the caller's choice) lands in buffer 0 again.
-template <int H, int K>
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// dp[MT0 .. MT0+NMT) of W^T dl from backward fragments [NMT][KB][64] at buf;
+// b holds dl as B operands.
+template <int KB, int NMT, int MT0, int MTP>
+__device__ __forceinline__ void dgrad_rows(const __bf16* buf, const bf16x8 (&b)[KB], float (&dp)[MTP][4],
+                                           int lane) {
+  const bf16x8* frag = reinterpret_cast<const bf16x8*>(buf);
+#pragma unroll
+  for (int mt = 0; mt < NMT; ++mt) {
+    f32x4 acc = zero4();
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[i];
+  }
+}
+
+// dp += W_sel^T dl_sel for the selection tile: 16x16x16 A operands [MTP][64]
+// at buf, bs = the tile's deltas as the B operand. Its own accumulator, added
+// with VALU (chaining a 16x16x16 MFMA onto a 16x16x32 accumulator gave
+// non-reproducible results with this toolchain).
+template <int MTP>
+__device__ __forceinline__ void dgrad_sel(const __bf16* buf, const bf16x4& bs, float (&dp)[MTP][4], int lane) {
+  const bf16x4* frag = reinterpret_cast<const bf16x4*>(buf);
+#pragma unroll
+  for (int mt = 0; mt < MTP; ++mt) {
+    const f32x4 sel = mfma_bf16_16(frag[mt * 64 + lane], bs, zero4());
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dp[mt][i] += sel[i];
+  }
+}
+
+// Stage order of one tile's forward: layer 0, hidden layers 1..NH-1, then the
+// output layer in NOUT stages (two halves of its row tiles when its
+// fragments exceed a buffer); stage s computes from buffer s % 2 while stage
+// s + 1 is copied into the other. The functions take the buffer pointers by
+// reference and swap them where a layer ends on the other parity, so that
+// "resident in b0" always names the buffer the next stage computes from.
+// SEL = 1: one more output tile, the selection logit (row 8K); ENC = 1:
+// layer 0 reads the encoded input.
+template <int H, int K, int SEL = 0, int ENC = 0>
 struct NetBf16 {
-  typedef Mlp<H, K, 1> M;
+  typedef Mlp<H, K, 1, ENC> M;
   typedef __bf16 W;
   static constexpr int NH = 4;
-  static constexpr int MTH = H / 16, MTO = K / 2, KQ = K / 4, HALF_O = MTO / 2;
-  static constexpr int KBO = K / 4;                        // 32-wide blocks over the 8K output rows
-  static constexpr int BUF = (H * H > 4 * K * H) ? H * H : 4 * K * H;   // elements per buffer
-  static constexpr int OB_HALF = (H / 32) * KBO * 512;    // half of the output layer's backward fragments
+  static constexpr int MTH = H / 16, MTO = K / 2 + SEL, KQ = K / 4;
+  static constexpr int KBO = K / 4;                        // 32-wide blocks over the 8K lobe rows
+  static constexpr int L0 = H * M::IN;                     // layer 0's forward fragments (elements)
+  static constexpr int OUT = MTO * 16 * H;                 // the output layer's forward fragments
+  static constexpr int OB = 8 * K * H + SEL * 16 * H;      // its backward fragments (+ the selection tile's)
+  static constexpr int NOUT = OUT > H * H ? 2 : 1;         // stages of the output layer
+  static constexpr int HALF_O = MTO / 2;
+  static constexpr int OUT_STAGE = OUT / NOUT, OB_STAGE = OB / NOUT;
+  static constexpr int BUF = cmax(cmax(H * H, L0), cmax(OUT_STAGE, OB_STAGE));   // elements per buffer
   static constexpr int SP = kWGV + 8;                      // staging pitch (bf16)
   static constexpr int RMAX = 8 * K;
   static_assert(NH % 2 == 0, "buffer parity assumes an even number of hidden layers");
-  static_assert(H * H <= BUF && 4 * K * H <= BUF && OB_HALF <= BUF, "stage exceeds a buffer");
+  static_assert(NOUT == 1 || (SEL == 0 && MTO % 2 == 0 && MTH % 2 == 0), "a two-stage output layer splits evenly");
+  static_assert(BUF * 2 <= 16384 * 2, "two 32 KiB weight buffers");
 
-  __device__ static Bf16Layout layout() { return Bf16Layout{NetDims{H, NH, K}}; }
+  __device__ static Bf16Layout layout() { return Bf16Layout{NetDims{H, NH, K, SEL, ENC}}; }
   __device__ static void dma(W* dst, const W* src, int elems) { lds_dma(dst, src, elems * 2); }
   __device__ static void sync_stage() {
     lds_dma_wait();
     __syncthreads();
   }
+  __device__ static void swap(W*& a, W*& b) {
+    W* t = a;
+    a = b;
+    b = t;
+  }
   // Layer 0 into b0, awaited: the first tile of a workgroup.
   __device__ static void begin(const W* wg, W* b0) {
-    dma(b0, wg + layout().fwd_off(0), H * 16);
+    dma(b0, wg + layout().fwd_off(0), L0);
     sync_stage();
   }
 
   // Hidden layers of one tile with layer 0 resident in b0: hp[l] receives
-  // hidden layer l's activations as B operands; `next` (elems) is in b0 on
-  // return (a full forward puts the output layer's first half there).
-  __device__ static void hidden(const W* wg, W* b0, W* b1, const typename M::Input& x, Pk<MTH> (&hp)[NH],
+  // hidden layer l's activations as B operands; `next` (elems) is resident
+  // in b0 on return (a full forward puts the output layer's first stage there).
+  __device__ static void hidden(const W* wg, W*& b0, W*& b1, const typename M::Input& x, Pk<MTH> (&hp)[NH],
                                 const W* next, int next_elems, int lane) {
     const Bf16Layout Lt = layout();
     float y[MTH][4];
@@ -137,60 +195,72 @@ struct NetBf16 {
   }
 
   // Output layer from the last hidden layer's activations, with its first
-  // half resident in b0; leaves `next` (elems) in b0 on return.
-  __device__ static void output(const W* wg, W* b0, W* b1, const Pk<MTH>& hl, float (&out)[MTO][4],
+  // stage resident in b0; leaves `next` (elems) resident in b0 on return.
+  __device__ static void output(const W* wg, W*& b0, W*& b1, const Pk<MTH>& hl, float (&out)[MTO][4],
                                 const W* next, int next_elems, int lane) {
     const Bf16Layout Lt = layout();
     bf16x8 b[M::KBH];
     hl.ops(b);
-    dma(b1, wg + Lt.fwd_off(NH) + HALF_O * 16 * H, HALF_O * 16 * H);
-    {
-      float part[HALF_O][4];
-      M::template gemm_op<HALF_O>(b0, b, part, lane);
+    if constexpr (NOUT == 2) {
+      dma(b1, wg + Lt.fwd_off(NH) + OUT_STAGE, OUT_STAGE);
+      {
+        float part[HALF_O][4];
+        M::template gemm_op<HALF_O>(b0, b, part, lane);
 #pragma unroll
-      for (int mt = 0; mt < HALF_O; ++mt)
+        for (int mt = 0; mt < HALF_O; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[mt][i] = part[mt][i];
+          for (int i = 0; i < 4; ++i) out[mt][i] = part[mt][i];
+      }
+      sync_stage();
+      dma(b0, next, next_elems);
+      {
+        float part[HALF_O][4];
+        M::template gemm_op<HALF_O>(b1, b, part, lane);
+#pragma unroll
+        for (int mt = 0; mt < HALF_O; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) out[HALF_O + mt][i] = part[mt][i];
+      }
+      sync_stage();
+    } else {
+      dma(b1, next, next_elems);
+      M::template gemm_op<MTO>(b0, b, out, lane);
+      sync_stage();
+      swap(b0, b1);
     }
-    sync_stage();
-    dma(b0, next, next_elems);
-    {
-      float part[HALF_O][4];
-      M::template gemm_op<HALF_O>(b1, b, part, lane);
-#pragma unroll
-      for (int mt = 0; mt < HALF_O; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[HALF_O + mt][i] = part[mt][i];
-    }
-    sync_stage();
   }
 
   // Full forward of one tile with layer 0 resident in b0; the next tile's
-  // layer 0 is resident in b0 on return (query, gradient).
-  __device__ static void forward(const W* wg, W* b0, W* b1, const typename M::Input& x, float (&out)[MTO][4],
+  // layer 0 is resident in b0 on return (query).
+  __device__ static void forward(const W* wg, W*& b0, W*& b1, const typename M::Input& x, float (&out)[MTO][4],
                                  int lane) {
     const Bf16Layout Lt = layout();
     Pk<MTH> hp[NH];
-    hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), HALF_O * 16 * H, lane);   // output half 0 -> b0
-    output(wg, b0, b1, hp[NH - 1], out, wg + Lt.fwd_off(0), H * 16, lane);
+    hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), OUT_STAGE, lane);   // output stage 0 -> b0
+    output(wg, b0, b1, hp[NH - 1], out, wg + Lt.fwd_off(0), L0, lane);
+  }
+
+  // dh = W_out^T dl with the output layer's first backward stage resident in
+  // b0: bo holds dl's 8K lobe rows as B operands, bs the selection tile's.
+  // `next` (elems) is resident in b0 on return.
+  __device__ static void out_dgrad(const W* out_bwd, W*& b0, W*& b1, const bf16x8 (&bo)[KBO], const bf16x4& bs,
+                                   float (&dh)[MTH][4], const W* next, int next_elems, int lane) {
+    if constexpr (NOUT == 2) {
+      dma(b1, out_bwd + OB_STAGE, OB_STAGE);
+      dgrad_rows<KBO, MTH / 2, 0>(b0, bo, dh, lane);
+      sync_stage();
+      dma(b0, next, next_elems);
+      dgrad_rows<KBO, MTH / 2, MTH / 2>(b1, bo, dh, lane);
+      sync_stage();
+    } else {
+      dma(b1, next, next_elems);
+      dgrad_rows<KBO, MTH, 0>(b0, bo, dh, lane);
+      if constexpr (SEL == 1) dgrad_sel(b0 + 8 * K * H, bs, dh, lane);
+      sync_stage();
+      swap(b0, b1);
+    }
   }
 };
-
-// dp[MT0 .. MT0+NMT) of W^T dl from backward fragments [NMT][KB][64] at buf;
-// b holds dl as B operands.
-template <int KB, int NMT, int MT0, int MTP>
-__device__ __forceinline__ void dgrad_rows(const __bf16* buf, const bf16x8 (&b)[KB], float (&dp)[MTP][4],
-                                           int lane) {
-  const bf16x8* frag = reinterpret_cast<const bf16x8*>(buf);
-#pragma unroll
-  for (int mt = 0; mt < NMT; ++mt) {
-    f32x4 acc = zero4();
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[i];
-  }
-}
 
 // ------------------------------------------------------------------ FP32 ----
 template <int H, int K>
@@ -285,8 +355,8 @@ struct NetF32 {
   }
 };
 
-template <int H, int K, int PREC>
-using LargeNet = typename std::conditional<PREC == 1, NetBf16<H, K>, NetF32<H, K>>::type;
+template <int H, int K, int PREC, int SEL, int ENC>
+using LargeNet = typename std::conditional<PREC == 1, NetBf16<H, K, SEL, ENC>, NetF32<H, K>>::type;
 
 // Hidden activations kept by the FP32 backward kernels (the BF16 ones keep
 // them packed, as Pk).
@@ -324,57 +394,50 @@ __device__ __forceinline__ void stage_act(S* st, const Act<PREC, MTH>& h, int wa
 }
 
 // dL/d(raw outputs) of 16 vertices: BF16 as the output layer's dgrad B
-// operands (K/4 16-byte slots per lane); FP32 as the accumulator image
-// (K/2 16-byte slots per lane).
-template <int K, int PREC>
+// operands (K/4 16-byte slots per lane, then with the selection output one
+// 8-byte slot of the selection tile's 16x16x16 operand); FP32 as the
+// accumulator image (K/2 16-byte slots per lane).
+template <int K, int PREC, int SEL = 0>
 struct DOut {
   static constexpr int MTO = K / 2, KBO = K / 4;
+  static constexpr int BLOCK = 64 * (8 * KBO + 4 * SEL);   // BF16 elements per 16 vertices
+  static_assert(PREC == 1 || SEL == 0, "the FP32 image has no selection tile");
   __device__ static void store(void* base, int64_t tile16, const float (&dl)[MTO][4], int lane) {
-    if constexpr (PREC == 1) {
-      bf16x8* d = reinterpret_cast<bf16x8*>(base) + tile16 * KBO * 64 + lane;
+    float4* d = reinterpret_cast<float4*>(base) + tile16 * MTO * 64 + lane;
 #pragma unroll
-      for (int kb = 0; kb < KBO; ++kb) {
-        bf16x8 b;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) b[j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
-        d[kb * 64] = b;
-      }
-    } else {
-      float4* d = reinterpret_cast<float4*>(base) + tile16 * MTO * 64 + lane;
-#pragma unroll
-      for (int mt = 0; mt < MTO; ++mt) d[mt * 64] = float4{dl[mt][0], dl[mt][1], dl[mt][2], dl[mt][3]};
-    }
+    for (int mt = 0; mt < MTO; ++mt) d[mt * 64] = float4{dl[mt][0], dl[mt][1], dl[mt][2], dl[mt][3]};
   }
   __device__ static void load(const void* base, int64_t tile16, float (&dl)[MTO][4], int lane) {
-    if constexpr (PREC == 1) {
-      const bf16x8* s = reinterpret_cast<const bf16x8*>(base) + tile16 * KBO * 64 + lane;
+    const float4* s = reinterpret_cast<const float4*>(base) + tile16 * MTO * 64 + lane;
 #pragma unroll
-      for (int kb = 0; kb < KBO; ++kb) {
-        const bf16x8 b = s[kb * 64];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dl[2 * kb + (j >> 2)][j & 3] = (float)b[j];
-      }
-    } else {
-      const float4* s = reinterpret_cast<const float4*>(base) + tile16 * MTO * 64 + lane;
-#pragma unroll
-      for (int mt = 0; mt < MTO; ++mt) {
-        const float4 x = s[mt * 64];
-        dl[mt][0] = x.x; dl[mt][1] = x.y; dl[mt][2] = x.z; dl[mt][3] = x.w;
-      }
+    for (int mt = 0; mt < MTO; ++mt) {
+      const float4 x = s[mt * 64];
+      dl[mt][0] = x.x; dl[mt][1] = x.y; dl[mt][2] = x.z; dl[mt][3] = x.w;
     }
   }
-  // BF16 only: the stored slots are exactly the output layer's dgrad B operands
-  __device__ static void load_operands(const void* base, int64_t tile16, bf16x8 (&b)[KBO], int lane) {
-    const bf16x8* s = reinterpret_cast<const bf16x8*>(base) + tile16 * KBO * 64 + lane;
+  // BF16: the stored slots are exactly the output layer's dgrad B operands
+  __device__ static void store_operands(void* base, int64_t tile16, const bf16x8 (&b)[KBO], const bf16x4& bs,
+                                        int lane) {
+    __bf16* blk = reinterpret_cast<__bf16*>(base) + tile16 * BLOCK;
+    bf16x8* d = reinterpret_cast<bf16x8*>(blk) + lane;
+#pragma unroll
+    for (int kb = 0; kb < KBO; ++kb) d[kb * 64] = b[kb];
+    if constexpr (SEL == 1) reinterpret_cast<bf16x4*>(blk + KBO * 512)[lane] = bs;
+  }
+  __device__ static void load_operands(const void* base, int64_t tile16, bf16x8 (&b)[KBO], bf16x4& bs, int lane) {
+    const __bf16* blk = reinterpret_cast<const __bf16*>(base) + tile16 * BLOCK;
+    const bf16x8* s = reinterpret_cast<const bf16x8*>(blk) + lane;
 #pragma unroll
     for (int kb = 0; kb < KBO; ++kb) b[kb] = s[kb * 64];
+    if constexpr (SEL == 1) bs = reinterpret_cast<const bf16x4*>(blk + KBO * 512)[lane];
   }
 };
 
 // ---------------------------------------------------------------- query ----
-template <int H, int K, int PREC, int MODE>
+// MODE 0: query, 1: raw forward only
+template <int H, int K, int PREC, int SEL, int ENC, int MODE>
 __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
-  typedef LargeNet<H, K, PREC> N;
+  typedef LargeNet<H, K, PREC, SEL, ENC> N;
   typedef typename N::M M;
   typedef typename N::W W;
   constexpr int KQ = N::KQ;
@@ -400,6 +463,7 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
           const int p = t / KQ, k = g * KQ + t % KQ;
           a.raw_out[(int64_t)(p * K + k) * a.ld + v] = out[t >> 2][t & 3];
         }
+        if (SEL == 1 && g == 0) a.raw_out[(int64_t)(8 * K) * a.ld + v] = out[N::MTO - 1][0];
       }
       continue;
     }
@@ -419,6 +483,8 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
       a.dir_out[a.ld + v] = vy;
       a.dir_out[2 * a.ld + v] = vz;
       a.pdf_out[v] = fexp(logq);
+      // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
+      if (SEL == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[N::MTO - 1][0]));
     }
     if (a.rec_out != nullptr && valid) {
       float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
@@ -435,9 +501,11 @@ __global__ __launch_bounds__(256) void large_query_kernel(QueryArgs a) {
 }
 
 // ------------------------------------------------------------- gradient ----
-template <int H, int K, int PREC>
+// FP32 path: forward and the weighted-NLL / NASG backward, storing dL/d(raw
+// outputs) and the loss partials.
+template <int H, int K>
 __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
-  typedef LargeNet<H, K, PREC> N;
+  typedef NetF32<H, K> N;
   typedef typename N::M M;
   typedef typename N::W W;
   constexpr int KQ = N::KQ, MTO = N::MTO;
@@ -450,7 +518,6 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
   const int wave = threadIdx.x >> 6;
   const float inv_b = 1.0f / (float)a.B;
   double loss_sum = 0.0, w_sum = 0.0;
-  if constexpr (PREC == 1) N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * kWGV + wave * 16 + c;
@@ -474,7 +541,7 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
       loss_sum += (double)wj * (double)(-logq);
       w_sum += (double)wj;
     }
-    DOut<K, PREC>::store(a.dout, tile * 4 + wave, dl, lane);
+    DOut<K, 0>::store(a.dout, tile * 4 + wave, dl, lane);
   }
   __shared__ double red[4][2];
 #pragma unroll
@@ -506,38 +573,44 @@ constexpr int kBwdWaves = 8;
 constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
 constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
 
-template <int H, int K, int GROUP>
+template <int H, int K, int SEL, int ENC, int GROUP>
 __global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bwd_bf16_kernel(LargeTrainArgs a) {
-  typedef NetBf16<H, K> N;
+  typedef NetBf16<H, K, SEL, ENC> N;
   typedef typename N::M M;
   typedef __bf16 W;
-  typedef __bf16 S;
+  typedef __bf16 St;   // staging element
+  typedef DOut<K, 1, SEL> DO;
   constexpr int NH = N::NH, MTH = N::MTH, MTO = N::MTO, KBO = N::KBO, SP = kBwdSP;
   constexpr int CTH = H / 16, HALF_H = MTH / 2, KBH = MTH / 2;
-  static_assert(MTH == kBwdWaves && MTO == 2 * kBwdWaves, "one hidden row tile per wave");
+  constexpr int CT0 = M::IN / 16;                   // column tiles of layer 0
+  static_assert(MTH == kBwdWaves, "one hidden row tile per wave");
+  static_assert(N::NOUT == 2 ? MTO == 2 * kBwdWaves : MTO <= kBwdWaves, "output row tiles per wave");
+  static_assert(MTO / N::NOUT * 16 <= H && M::IN <= H, "staging holds H rows");
   extern __shared__ __align__(16) unsigned char smem[];
   W* bufA = reinterpret_cast<W*>(smem);
   W* bufB = bufA + N::BUF;
-  S* dst = reinterpret_cast<S*>(smem + 2 * N::BUF * sizeof(W));   // [H rows][SP]
-  S* hst = dst + H * SP;                                           // [H rows][SP]
+  St* dst = reinterpret_cast<St*>(smem + 2 * N::BUF * sizeof(W));   // [H rows][SP]
+  St* hst = dst + H * SP;                                            // [H rows][SP]
   const W* wg = reinterpret_cast<const W*>(a.wpack);
   const Bf16Layout Lt = N::layout();
-  const NetDims dims{H, NH, K};
-  const W* out_bwd = wg + Lt.bwd_off(NH);   // [H/16][KBO][64][8]: halves over the first index
+  const NetDims dims = Lt.d;
+  const W* out_bwd = wg + Lt.bwd_off(NH);   // the output layer's backward fragments
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
-  const int rt[1] = {wave};                 // this wave's row tile (+ MTH for the output layer's 2nd half)
+  const int rt[1] = {wave};                 // this wave's row tile (+ MTH for a two-stage output layer)
   const int rt_hi[1] = {wave + MTH};
+  const int n_out_rt = (N::NOUT == 2 || wave < MTO) ? 1 : 0;   // output row tiles this wave owns
 
-  constexpr int NO = GROUP == 0 ? 2 : 1;            // output layer halves (group 0)
+  constexpr int NO = GROUP == 0 ? N::NOUT : 1;      // output layer stages (group 0)
   constexpr int NM = GROUP == 1 ? NH - 2 : 1;       // hidden layers NH-2..1 (group 1)
   f32x4 accO[NO][1][CTH];
   f32x4 accT[1][CTH];                               // layer NH-1 (group 0)
   f32x4 accM[NM][1][CTH];
-  f32x4 acc0[1][1];                                 // layer 0 (group 1)
-  acc0[0][0] = zero4();
+  f32x4 acc0[1][CT0];                               // layer 0 (group 1)
+#pragma unroll
+  for (int ct = 0; ct < CT0; ++ct) acc0[0][ct] = zero4();
 #pragma unroll
   for (int ct = 0; ct < CTH; ++ct) {
     accT[0][ct] = zero4();
@@ -555,72 +628,85 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
   const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t v = tile * kBwdV + wave * 16 + c;
+    const int64_t blk = tile * kBwdWaves + wave;   // this wave's 16-vertex block
     const bool valid = v < a.B;
     typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
     Pk<MTH> hp[NH];
     bf16x8 bo[KBO];
+    bf16x4 bs = {};
     if constexpr (GROUP == 1) {
-      float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f;
+      float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f, pfs = 0.0f;
       if (valid) {
         vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
         wj = a.w[v];
+        if constexpr (SEL == 1) pfs = a.bsdf_pdf[v];
       }
-      N::hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), N::HALF_O * 16 * H, lane);   // output half 0 -> b0
+      N::hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), N::OUT_STAGE, lane);    // output stage 0 -> b0
       float out[MTO][4];
-      N::output(wg, b0, b1, hp[NH - 1], out, out_bwd, N::OB_HALF, lane);          // output-dgrad half 0 -> b0
+      N::output(wg, b0, b1, hp[NH - 1], out, out_bwd, N::OB_STAGE, lane);      // output-dgrad stage 0 -> b0
       const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
       const float gs = valid ? -wj * inv_b : 0.0f;
       float dl[MTO][4];
-      const float logq = train_epilogue<N::KQ, MTO>(out, vx, vy, vz, gs, valid, a.eps, dl, 0.0f, 0.0f, a.amul);
+      const float lterm =
+          train_epilogue<N::KQ, MTO, SEL>(out, vx, vy, vz, gs, valid, a.eps, dl, pfs, a.mis_e, a.amul);
       if (valid && g == 0) {
-        loss_sum += (double)wj * (double)(-logq);
+        loss_sum += (double)wj * (double)(-lterm);
         w_sum += (double)wj;
       }
 #pragma unroll
       for (int kb = 0; kb < KBO; ++kb)
 #pragma unroll
         for (int j = 0; j < 8; ++j) bo[kb][j] = (__bf16)dl[2 * kb + (j >> 2)][j & 3];
-      bf16x8* d = reinterpret_cast<bf16x8*>(a.dout) + (tile * kBwdWaves + wave) * KBO * 64 + lane;
+      if constexpr (SEL == 1) {
 #pragma unroll
-      for (int kb = 0; kb < KBO; ++kb) d[kb * 64] = bo[kb];
+        for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[MTO - 1][j];
+      }
+      DO::store_operands(a.dout, blk, bo, bs, lane);
     } else {
-      N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_HALF, lane);   // leaves output-dgrad half 0 in b0
-      DOut<K, 1>::load_operands(a.dout, tile * kBwdWaves + wave, bo, lane);
+      N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_STAGE, lane);   // leaves output-dgrad stage 0 in b0
+      DO::load_operands(a.dout, blk, bo, bs, lane);
     }
     float dh[MTH][4];
     Pk<MTH> dhw;
     if constexpr (GROUP == 0) {
       Pk<MTO> dlw;
       dlw.from_ops(bo);
-      dlw.template stage<SP, 0, MTH>(dst, wave, lane);           // output rows [0, 8K/2)
+      if constexpr (SEL == 1) dlw.set_last(bs);
       hp[NH - 1].template stage<SP>(hst, wave, lane);
-      N::dma(b1, out_bwd + N::OB_HALF, N::OB_HALF);
-      dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
-      N::sync_stage();                                            // also publishes the staging
-      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[0], lane);
-      N::dma(b0, wg + Lt.fwd_off(0), H * 16);                     // the next tile's layer 0
-      dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
-      dhw.masked(dh, hp[NH - 1]);
-      N::sync_stage();                                            // the first half has been read
-      dlw.template stage<SP, MTH, MTH>(dst, wave, lane);          // output rows [8K/2, 8K)
-      __syncthreads();
-      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[1], lane);
+      if constexpr (N::NOUT == 2) {
+        dlw.template stage<SP, 0, MTH>(dst, wave, lane);           // output rows [0, 8K/2)
+        N::dma(b1, out_bwd + N::OB_STAGE, N::OB_STAGE);
+        dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
+        N::sync_stage();                                            // also publishes the staging
+        wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[0], lane);
+        N::dma(b0, wg + Lt.fwd_off(0), N::L0);                      // the next tile's layer 0
+        dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
+        dhw.masked(dh, hp[NH - 1]);
+        N::sync_stage();                                            // the first half has been read
+        dlw.template stage<SP, MTH, MTH>(dst, wave, lane);          // output rows [8K/2, 8K)
+        __syncthreads();
+        wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[N::NOUT - 1], lane);
+      } else {
+        dlw.template stage<SP, 0, MTO>(dst, wave, lane);            // every output row
+        N::dma(b1, wg + Lt.fwd_off(0), N::L0);                      // the next tile's layer 0
+        dgrad_rows<KBO, MTH, 0>(b0, bo, dh, lane);
+        if constexpr (SEL == 1) dgrad_sel(b0 + 8 * K * H, bs, dh, lane);
+        N::sync_stage();                                            // also publishes the staging
+        N::swap(b0, b1);
+        wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, n_out_rt, accO[0], lane);
+        dhw.masked(dh, hp[NH - 1]);
+      }
       __syncthreads();
       dhw.template stage<SP>(dst, wave, lane);
       hp[NH - 2].template stage<SP>(hst, wave, lane);
       __syncthreads();
-      wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accT, lane);
+      wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accT, lane);
       // the next writes to the staging area follow the next tile's forward,
       // whose barriers order them after these reads
     } else {
-      N::dma(b1, out_bwd + N::OB_HALF, N::OB_HALF);
-      dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
-      N::sync_stage();
-      N::dma(b0, wg + Lt.bwd_off(NH - 1), H * H);
-      dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
+      N::out_dgrad(out_bwd, b0, b1, bo, bs, dh, wg + Lt.bwd_off(NH - 1), H * H, lane);   // layer NH-1 -> b0
       dhw.masked(dh, hp[NH - 1]);
-      N::sync_stage();
       Pk<MTH> d2w;
       {
         bf16x8 op[KBH];
@@ -638,7 +724,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
         d2w.template stage<SP>(dst, wave, lane);
         hp[l - 1].template stage<SP>(hst, wave, lane);
         if (l > 1) N::dma(oth, wg + Lt.bwd_off(l - 1), H * H);
-        else N::dma(oth, wg + Lt.fwd_off(0), H * 16);             // the next tile's layer 0
+        else N::dma(oth, wg + Lt.fwd_off(0), N::L0);              // the next tile's layer 0
         bf16x8 op[KBH];
         d2w.ops(op);
         float dn[MTH][4];
@@ -646,15 +732,15 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
         Pk<MTH> dnw;
         dnw.masked(dn, hp[l - 1]);
         N::sync_stage();                                          // also publishes the staging
-        wgrad_tiles<1, S, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accM[l - 1], lane);
+        wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accM[l - 1], lane);
         __syncthreads();
         d2w = dnw;
         W* t = cur; cur = oth; oth = t;
       }
       d2w.template stage<SP>(dst, wave, lane);
-      M::template stage_input<S, SP>(hst, x, wave, lane);
+      M::template stage_input<St, SP>(hst, x, wave, lane);
       __syncthreads();
-      wgrad_tiles<1, S, SP, 1, 1, kBwdV>(dst, hst, rt, 1, acc0, lane);
+      wgrad_tiles<1, St, SP, 1, CT0, kBwdV>(dst, hst, rt, 1, acc0, lane);
       b0 = cur;   // the next tile's layer 0
       b1 = oth;
     }
@@ -662,13 +748,13 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
 
   float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
   if constexpr (GROUP == 0) {
-    flush_tiles<1, CTH>(part, dims, NH, rt, 1, accO[0], lane);
-    flush_tiles<1, CTH>(part, dims, NH, rt_hi, 1, accO[1], lane);
+    flush_tiles<1, CTH>(part, dims, NH, rt, n_out_rt, accO[0], lane);
+    if constexpr (N::NOUT == 2) flush_tiles<1, CTH>(part, dims, NH, rt_hi, 1, accO[N::NOUT - 1], lane);
     flush_tiles<1, CTH>(part, dims, NH - 1, rt, 1, accT, lane);
   } else {
 #pragma unroll
     for (int l = 1; l <= NH - 2; ++l) flush_tiles<1, CTH>(part, dims, l, rt, 1, accM[l - 1], lane);
-    flush_tiles<1, 1>(part, dims, 0, rt, 1, acc0, lane);
+    flush_tiles<1, CT0>(part, dims, 0, rt, 1, acc0, lane);
     // loss partials: wave reduction, then the waves in order
     __shared__ double red[kBwdWaves][2];
 #pragma unroll
@@ -810,20 +896,21 @@ static hipError_t set_lds(Kern kern, size_t bytes) {
 }
 
 // LDS of the weight buffers, and of the backward kernels (weights + staging)
-template <int H, int K, int PREC>
+template <int H, int K, int PREC, int SEL, int ENC>
 struct LargeLds {
-  typedef LargeNet<H, K, PREC> N;
+  typedef LargeNet<H, K, PREC, SEL, ENC> N;
   static constexpr size_t fwd = (size_t)(PREC == 1 ? 2 : 1) * N::BUF * sizeof(typename N::W);
   static constexpr size_t bwd = PREC == 1 ? fwd + (size_t)2 * H * kBwdSP * sizeof(__bf16)
                                           : fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
   static constexpr int bwd_threads = PREC == 1 ? 64 * kBwdWaves : 256;
   static_assert(bwd <= 160 * 1024, "LDS budget");
+  static_assert(PREC == 1 || (SEL == 0 && ENC == 0), "the FP32 network has neither option");
 };
 
-template <int H, int K, int PREC>
+template <int H, int K, int PREC, int SEL, int ENC>
 static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t st) {
-  const size_t shmem = LargeLds<H, K, PREC>::fwd;
-  auto kern = mode == 0 ? large_query_kernel<H, K, PREC, 0> : large_query_kernel<H, K, PREC, 1>;
+  const size_t shmem = LargeLds<H, K, PREC, SEL, ENC>::fwd;
+  auto kern = mode == 0 ? large_query_kernel<H, K, PREC, SEL, ENC, 0> : large_query_kernel<H, K, PREC, SEL, ENC, 1>;
   static bool attr[2] = {false, false};
   if (!attr[mode]) {
     hipError_t e = set_lds(kern, shmem);
@@ -837,53 +924,76 @@ static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t
   return hipGetLastError();
 }
 
+// BF16: the backward kernels' grid, one workgroup per 128-vertex tile up to
+// one per CU; FP32: the backward kernels' 64-vertex tiles
+int large_train_workgroups(int64_t B, int num_cus, int prec) {
+  if (prec != 1) return train_workgroups(B, num_cus);
+  const int64_t t = (B + kBwdV - 1) / kBwdV;
+  const int64_t cap = num_cus < kMaxTrainWG ? num_cus : kMaxTrainWG;
+  return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
+}
+
 int large_loss_workgroups(int64_t B, int num_cus, int prec) {
-  if (prec == 1) return train_workgroups(B, num_cus);   // the fused backward kernel's grid
-  const int64_t t = (B + kWGV - 1) / kWGV;               // the FP32 gradient kernel: two per CU
+  if (prec == 1) return large_train_workgroups(B, num_cus, prec);   // the fused backward kernel's grid
+  const int64_t t = (B + kWGV - 1) / kWGV;                           // the FP32 gradient kernel: two per CU
   const int64_t cap = 2LL * (num_cus < kMaxTrainWG ? num_cus : kMaxTrainWG);
   return (int)(t < cap ? (t < 1 ? 1 : t) : cap);
 }
 
-template <int H, int K, int PREC>
+// dL/d(raw outputs) images of a batch of up to B vertices, rounded up to
+// whole backward tiles: out_rows values per vertex (BF16 or FP32)
+size_t large_dout_bytes(int64_t B, int K, int S, int prec) {
+  const int64_t v = (B + kBwdV - 1) / kBwdV * kBwdV;
+  return (size_t)v * (size_t)(8 * K + 16 * S) * (prec == 1 ? 2 : 4);
+}
+
+template <int H, int K, int PREC, int SEL, int ENC>
 static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_grad, hipStream_t st) {
-  const size_t sh_fwd = LargeLds<H, K, PREC>::fwd;
-  const size_t sh_bwd = LargeLds<H, K, PREC>::bwd;
-  auto k_grad = gradout_kernel<H, K, PREC>;
-  auto k_bwd0 = PREC == 1 ? bwd_bf16_kernel<H, K, 0> : bwd_f32_kernel<H, K, 0>;
-  auto k_bwd1 = PREC == 1 ? bwd_bf16_kernel<H, K, 1> : bwd_f32_kernel<H, K, 1>;
+  typedef LargeLds<H, K, PREC, SEL, ENC> Lds;
   static bool attr = false;
-  if (!attr) {
-    hipError_t e = PREC == 1 ? hipSuccess : set_lds(k_grad, sh_fwd);
-    if (e == hipSuccess) e = set_lds(k_bwd0, sh_bwd);
-    if (e == hipSuccess) e = set_lds(k_bwd1, sh_bwd);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  const int bt = LargeLds<H, K, PREC>::bwd_threads;
-  if (PREC == 1) {
+  if constexpr (PREC == 1) {
+    auto k_bwd0 = bwd_bf16_kernel<H, K, SEL, ENC, 0>;
+    auto k_bwd1 = bwd_bf16_kernel<H, K, SEL, ENC, 1>;
+    if (!attr) {
+      hipError_t e = set_lds(k_bwd0, Lds::bwd);
+      if (e == hipSuccess) e = set_lds(k_bwd1, Lds::bwd);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
     // the group-1 kernel computes and stores the raw-output gradient first
-    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
-    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
   } else {
-    hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), sh_fwd, st, a);
-    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(bt), sh_bwd, st, a);
-    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(bt), sh_bwd, st, a);
+    auto k_grad = gradout_kernel<H, K>;
+    auto k_bwd0 = bwd_f32_kernel<H, K, 0>;
+    auto k_bwd1 = bwd_f32_kernel<H, K, 1>;
+    if (!attr) {
+      hipError_t e = set_lds(k_grad, Lds::fwd);
+      if (e == hipSuccess) e = set_lds(k_bwd0, Lds::bwd);
+      if (e == hipSuccess) e = set_lds(k_bwd1, Lds::bwd);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), Lds::fwd, st, a);
+    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_large_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st) {
-#define NASG_CASE(h, k, p) \
-  if (H == h && K == k && prec == p) return launch_large_query_t<h, k, p>(a, mode, st);
+hipError_t launch_large_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st) {
+#define NASG_CASE(h, k, p, s, e) \
+  if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) return launch_large_query_t<h, k, p, s, e>(a, mode, st);
   NASG_FOR_EACH_LARGE_NET(NASG_CASE)
 #undef NASG_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_large_train(const LargeTrainArgs& a, int H, int K, int prec, int n_wg, int n_grad,
+hipError_t launch_large_train(const LargeTrainArgs& a, const NetDims& d, int prec, int n_wg, int n_grad,
                               hipStream_t st) {
-#define NASG_CASE(h, k, p) \
-  if (H == h && K == k && prec == p) return launch_large_train_t<h, k, p>(a, n_wg, n_grad, st);
+#define NASG_CASE(h, k, p, s, e) \
+  if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) \
+    return launch_large_train_t<h, k, p, s, e>(a, n_wg, n_grad, st);
   NASG_FOR_EACH_LARGE_NET(NASG_CASE)
 #undef NASG_CASE
   return hipErrorInvalidValue;

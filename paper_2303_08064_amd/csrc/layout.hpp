@@ -26,6 +26,10 @@ namespace nasg {
 
 constexpr int kInFeatures = 9;
 constexpr int kInPadded = 16;   // 9 features + constant one, zero-padded
+// Tab. "encoding": 19 one-blob bins per position coordinate (57), omega_o (3),
+// n (3) and the constant one: 64 inputs, no padding
+constexpr int kBlobBins = 19;
+constexpr int kInEncoded = 3 * kBlobBins + 6 + 1;
 
 // neuron feeding logical contraction index kl of the next layer
 NASG_HD int phys_bf16(int kl) { return (2 * (kl >> 5) + ((kl & 7) >> 2)) * 16 + 4 * ((kl & 31) >> 3) + (kl & 3); }
@@ -65,28 +69,34 @@ NASG_HD int inv_canon_out_row(int n, int K) {
 struct NetDims {
   int H, NH, K;
   int S = 0;   // 1: one more output, the selection probability (8K + 1 outputs)
+  int E = 0;   // 1: W_0 reads the encoded input (kInEncoded columns), else the 9 features + one
   NASG_HD int nout() const { return 8 * K + S; }
   NASG_HD int out_rows() const { return 8 * K + 16 * S; }   // physical, padded to whole tiles
   NASG_HD int layers() const { return NH + 1; }
   NASG_HD int rows(int l) const { return l == NH ? 8 * K + S : H; }
-  NASG_HD int cols(int l) const { return l == 0 ? kInFeatures + 1 : H; }
+  NASG_HD int in_cols() const { return E ? kInEncoded : kInFeatures + 1; }
+  NASG_HD int in_pad() const { return E ? kInEncoded : kInPadded; }   // layer 0's packed width
+  NASG_HD int cols(int l) const { return l == 0 ? in_cols() : H; }
   // canonical flat offset of W_l
   NASG_HD int64_t canon_off(int l) const {
     if (l == 0) return 0;
-    return (int64_t)H * (kInFeatures + 1) + (int64_t)(l - 1) * H * H;
+    return (int64_t)H * in_cols() + (int64_t)(l - 1) * H * H;
   }
   NASG_HD int64_t num_weights() const { return canon_off(NH) + (int64_t)(8 * K + S) * H; }
 };
 
 // ---- BF16 fragment layout (elements are bf16) ----
-// forward: L0 [H/16][64][4]; hidden l [H/16][H/32][64][8]; out [K/2 (+1)][H/32][64][8]
+// forward: L0 [H/16][64][4] (16x16x16 operands over the 16 padded inputs) or,
+// for the encoded input, [H/16][2][64][8] (16x16x32 operands, input k =
+// kb*32 + 8g + j in logical order); hidden l [H/16][H/32][64][8]; out
+// [K/2 (+1)][H/32][64][8]
 // backward (W^T): hidden l [H/16][H/32][64][8]; out [H/16][8K/32][64][8], then
 // for the selection tile the 16x16x16 A operands [H/16][64][4]
 struct Bf16Layout {
   NetDims d;
   NASG_HD int64_t fwd_off(int l) const {
     if (l == 0) return 0;
-    return (int64_t)d.H * 16 + (int64_t)(l - 1) * d.H * d.H;
+    return (int64_t)d.H * d.in_pad() + (int64_t)(l - 1) * d.H * d.H;
   }
   NASG_HD int64_t fwd_elems() const { return fwd_off(d.NH) + (int64_t)d.out_rows() * d.H; }
   NASG_HD int64_t bwd_off(int l) const {   // l >= 1
@@ -97,10 +107,10 @@ struct Bf16Layout {
 };
 
 // ---- FP32 row-major layout (elements are float) ----
-// layer l: [rows][cols_pad + 1] with cols_pad = 16 (l == 0) or H; output rows in physical order
+// layer l: [rows][cols_pad + 1] with cols_pad = 16 or 64 (l == 0) or H; output rows in physical order
 struct F32Layout {
   NetDims d;
-  NASG_HD int pitch(int l) const { return (l == 0 ? kInPadded : d.H) + 1; }
+  NASG_HD int pitch(int l) const { return (l == 0 ? d.in_pad() : d.H) + 1; }
   NASG_HD int64_t off(int l) const {
     if (l == 0) return 0;
     return (int64_t)d.H * pitch(0) + (int64_t)(l - 1) * d.H * pitch(1);
@@ -117,6 +127,10 @@ namespace nasg {
 NASG_HD int64_t bf16_fwd_pos(const Bf16Layout& Lt, int l, int n, int k) {
   const NetDims& d = Lt.d;
   if (l == 0) {
+    if (d.E) {
+      int mt = n >> 4, c = n & 15, kb = k >> 5, g = (k & 31) >> 3, j = k & 7;
+      return Lt.fwd_off(0) + ((int64_t)((mt * 2 + kb) * 64 + g * 16 + c) * 8 + j);
+    }
     int mt = n >> 4, c = n & 15, g = k >> 2, j = k & 3;
     return Lt.fwd_off(0) + ((int64_t)(mt * 64 + g * 16 + c) * 4 + j);
   }
@@ -151,6 +165,12 @@ NASG_HD void bf16_source(const Bf16Layout& Lt, int64_t e, int& l, int& n, int& k
   if (e < Lt.fwd_elems()) {
     if (e < Lt.fwd_off(1)) {
       l = 0;
+      if (d.E) {
+        int j = (int)(e & 7), lane = (int)((e >> 3) & 63), kb = (int)((e >> 9) & 1), mt = (int)(e >> 10);
+        n = mt * 16 + (lane & 15);
+        k = kb * 32 + (lane >> 4) * 8 + j;
+        return;
+      }
       int j = (int)(e & 3), lane = (int)((e >> 2) & 63), mt = (int)(e >> 8);
       n = mt * 16 + (lane & 15);
       k = (lane >> 4) * 4 + j;

@@ -10,21 +10,71 @@
 
 namespace nasg {
 
-template <int H, int K, int PREC>
+// The encoded input of Tab. "encoding" as the two 16x16x32 B operands of
+// layer 0: lane (g, c) holds inputs k = kb*32 + 8g + j (j = 0..7) of vertex
+// c. Input k < 57 is one-blob bin k % 19 of position coordinate k / 19: a
+// Gaussian of standard deviation 1/19 centred at the coordinate s, evaluated
+// at the bin centre (b + 1/2)/19, i.e. exp(-(19 s - b - 1/2)^2 / 2); then
+// omega_o (57..59), n (60..62) and the constant one (63). Computed in
+// registers from the 9 raw features: 36 bytes per vertex are read, not 256.
+struct EncodedInput {
+  bf16x8 b[2];
+};
+
+__device__ __forceinline__ EncodedInput load_encoded(const float* __restrict__ feat, int64_t ld, int64_t v,
+                                                     bool valid, int g) {
+  float p[3] = {0.0f, 0.0f, 0.0f}, dn[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = feat[(int64_t)i * ld + v];
+    if (g == 3) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) dn[i] = feat[(int64_t)(3 + i) * ld + v];
+    }
+  }
+  constexpr float kHalfLog2e = 0.72134752044448170368f;   // log2(e) / 2
+  EncodedInput x;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float val;
+      if (kb == 1 && j >= 1 && g == 3) {   // k = 57 + (j - 1): omega_o, n, then the one
+        val = j == 7 ? 1.0f : dn[j - 1];
+      } else {
+        const int k = kb * 32 + 8 * g + j;   // < 57
+        const int d = (k >= 2 * kBlobBins) ? 2 : (k >= kBlobBins ? 1 : 0);
+        const float s = d == 0 ? p[0] : (d == 1 ? p[1] : p[2]);
+        const float t = fmaf(s, (float)kBlobBins, -((float)(k - kBlobBins * d) + 0.5f));
+        val = __builtin_amdgcn_exp2f(-kHalfLog2e * t * t);
+      }
+      x.b[kb][j] = (__bf16)(valid ? val : 0.0f);
+    }
+  return x;
+}
+
+template <int H, int K, int PREC, int E = 0>
 struct Mlp;
 
 // ---------------------------------------------------------------- BF16 ----
-// 16x16x32 bf16 MFMA with FP32 accumulation; layer 0 uses 16x16x16.
-template <int H, int K>
-struct Mlp<H, K, 1> {
+// 16x16x32 bf16 MFMA with FP32 accumulation; layer 0 uses 16x16x16 over the
+// 16 padded raw inputs (E = 0) or 16x16x32 over the 64 encoded ones (E = 1).
+template <int H, int K, int E>
+struct Mlp<H, K, 1, E> {
   static constexpr int MTH = H / 16;     // row tiles of a hidden layer
   static constexpr int MTO = K / 2;      // row tiles of the output layer (8K/16)
   static constexpr int KBH = H / 32;     // 32-wide contraction blocks over a hidden layer
   static constexpr int KBO = K / 4;      // 32-wide contraction blocks over the output (8K/32)
-  typedef bf16x4 Input;
+  static constexpr int IN = E ? kInEncoded : kInPadded;   // layer 0's packed input width
+  typedef typename std::conditional<E == 1, EncodedInput, bf16x4>::type Input;
 
-  // features 4g..4g+3 of vertex v: p, omega_o, n, then the constant one, then zeros
+  // features 4g..4g+3 of vertex v: p, omega_o, n, then the constant one, then
+  // zeros; or the encoded input
   __device__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+    if constexpr (E == 1) return load_encoded(feat, ld, v, valid, g);
+    else return load_raw(feat, ld, v, valid, g);
+  }
+  __device__ static bf16x4 load_raw(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
     float f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -39,13 +89,21 @@ struct Mlp<H, K, 1> {
     return bf16x4{(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
   }
 
-  // layer 0's input (the values the forward used) into rows 0..15 of a
-  // [row][vertex] staging buffer at vertex column wave*16: rows 4g..4g+3
+  // layer 0's input (the values the forward used) into rows 0..IN-1 of a
+  // [row][vertex] staging buffer at vertex column wave*16: rows 4g..4g+3, or
+  // for the encoded input rows kb*32 + 8g .. + 7
   template <typename S, int SP>
   __device__ static void stage_input(S* st, const Input& x, int wave, int lane) {
     const int g = lane >> 4, c = lane & 15;
+    if constexpr (E == 1) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) st[(4 * g + j) * SP + wave * 16 + c] = (S)x[j];
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) st[(kb * 32 + 8 * g + j) * SP + wave * 16 + c] = (S)x.b[kb][j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) st[(4 * g + j) * SP + wave * 16 + c] = (S)x[j];
+    }
   }
 
   __device__ static bf16x8 operand(const float (&in)[2][4]) {
@@ -56,14 +114,12 @@ struct Mlp<H, K, 1> {
   }
 
   // h = relu(W_0 x)
-  __device__ static void layer0(const __bf16* lds, Input x, float (&h)[MTH][4], int lane) {
-    const bf16x4* frag = reinterpret_cast<const bf16x4*>(lds);
+  __device__ static void layer0(const __bf16* lds, const Input& x, float (&h)[MTH][4], int lane) {
+    layer0_linear(lds, x, h, lane);
 #pragma unroll
-    for (int mt = 0; mt < MTH; ++mt) {
-      f32x4 acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
+    for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[mt][i] = relu(acc[i]);
-    }
+      for (int i = 0; i < 4; ++i) h[mt][i] = relu(h[mt][i]);
   }
 
   // Next layer's B operands from a layer's pre-activation accumulators, the
@@ -88,11 +144,18 @@ struct Mlp<H, K, 1> {
   }
 
   // W_0 x without the ReLU
-  __device__ static void layer0_linear(const __bf16* lds, Input x, float (&y)[MTH][4], int lane) {
-    const bf16x4* frag = reinterpret_cast<const bf16x4*>(lds);
+  __device__ static void layer0_linear(const __bf16* lds, const Input& x, float (&y)[MTH][4], int lane) {
 #pragma unroll
     for (int mt = 0; mt < MTH; ++mt) {
-      f32x4 acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
+      f32x4 acc;
+      if constexpr (E == 1) {
+        const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+        acc = mfma_bf16_32(frag[(mt * 2) * 64 + lane], x.b[0], zero4());
+        acc = mfma_bf16_32(frag[(mt * 2 + 1) * 64 + lane], x.b[1], acc);
+      } else {
+        const bf16x4* frag = reinterpret_cast<const bf16x4*>(lds);
+        acc = mfma_bf16_16(frag[mt * 64 + lane], x, zero4());
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
     }
@@ -137,8 +200,9 @@ struct Mlp<H, K, 1> {
 
 // ---------------------------------------------------------------- FP32 ----
 // 16x16x4 f32 MFMA; weights row-major in LDS with an odd pitch.
-template <int H, int K>
-struct Mlp<H, K, 0> {
+template <int H, int K, int E>
+struct Mlp<H, K, 0, E> {
+  static_assert(E == 0, "the encoded input is compiled for BF16 networks");
   static constexpr int MTH = H / 16;
   static constexpr int MTO = K / 2;
   struct Input { float x[3]; };   // features kb*4 + g for kb = 0..2

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const float bc1 = (float)(1.0 - pow((double)a.beta1, t));
   const float bc2_sqrt = (float)sqrt(1.0 - pow((double)a.beta2, t));
   const float step_size = a.lr / bc1;
-  const NetDims d{a.H, a.NH, a.K, a.S};
+  const NetDims d{a.H, a.NH, a.K, a.S, a.E};
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n_weights; i += (int64_t)gridDim.x * 256) {
     const float gi = a.grad[i];
     const float m = fmaf(a.beta1, a.m[i], (1.0f - a.beta1) * gi);
@@ -431,8 +431,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ w, 
   }
 }
 
-hipError_t launch_pack(const float* w, void* wpack, int H, int NH, int K, int S, int prec, hipStream_t st) {
-  NetDims d{H, NH, K, S};
+hipError_t launch_pack(const float* w, void* wpack, const NetDims& d, int prec, hipStream_t st) {
   int64_t n = prec == 1 ? Bf16Layout{d}.total_elems() : F32Layout{d}.total_elems();
   int grid = (int)((n + 255) / 256);
   if (grid > 1024) grid = 1024;

@@ -37,21 +37,26 @@ def record_elems(n_lobes, B):
 class NasgGuide:
     """Device state of one guiding network plus its context in libnasg.so.
 
-    weights: flat float32 canonical weights (W_0 [hidden][10], W_1..W_{n-1}
-    [hidden][hidden], W_L [8K (+1)][hidden], each row-major), e.g. from
-    synth.flat_weights(synth.init_weights(...)).
+    weights: flat float32 canonical weights (W_0 [hidden][10] or, encoded,
+    [hidden][64], W_1..W_{n-1} [hidden][hidden], W_L [8K (+1)][hidden], each
+    row-major), e.g. from synth.flat_weights(synth.init_weights(...)).
     selection: the network has the selection-probability output and trains
     on the blended loss with fraction mis_fraction (Sec. 4.2).
     isotropic: a = 0 lobes (normalised spherical Gaussians), for comparisons.
+    encoded: W_0 reads the encoded input of Tab. "encoding" (one-blob bins of
+    the position, omega_o, n, the one), computed on the device from the same
+    9 raw features.
     """
 
     def __init__(self, weights, hidden=64, n_hidden=4, n_lobes=16, precision="bf16", eps=0.0,
                  lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, device="cuda",
-                 selection=False, mis_fraction=0.2, isotropic=False):
+                 selection=False, mis_fraction=0.2, isotropic=False, encoded=False):
         self.lib = load()
         self.cfg = Config(hidden, n_hidden, n_lobes, PRECISIONS[precision], eps, lr, beta1, beta2,
-                          adam_eps, max_batch, int(bool(selection)), mis_fraction, int(bool(isotropic)))
+                          adam_eps, max_batch, int(bool(selection)), mis_fraction, int(bool(isotropic)),
+                          int(bool(encoded)))
         self.selection = bool(selection)
+        self.encoded = bool(encoded)
         self.n_lobes = n_lobes
         self.hidden = hidden
         self.n_hidden = n_hidden
@@ -197,7 +202,7 @@ class NasgGuide:
 
     # -- views -----------------------------------------------------------------
     def layer_shapes(self):
-        s = [(self.hidden, 10)] + [(self.hidden, self.hidden)] * (self.n_hidden - 1)
+        s = [(self.hidden, 64 if self.encoded else 10)] + [(self.hidden, self.hidden)] * (self.n_hidden - 1)
         return s + [(self.n_out, self.hidden)]
 
     def split(self, flat):

@@ -52,8 +52,11 @@ def radiance_weights(n, rng):
     return np.exp(rng.standard_normal(n)).astype(np.float32)
 
 
-def layer_shapes(hidden, n_hidden, n_lobes, selection=False):
-    shapes = [(hidden, IN_FEATURES + 1)]
+ENCODED_INPUTS = 64   # W_0's columns with the encoded input of Tab. "encoding"
+
+
+def layer_shapes(hidden, n_hidden, n_lobes, selection=False, encoded=False):
+    shapes = [(hidden, ENCODED_INPUTS if encoded else IN_FEATURES + 1)]
     shapes += [(hidden, hidden)] * (n_hidden - 1)
     shapes.append((8 * n_lobes + (1 if selection else 0), hidden))
     return shapes

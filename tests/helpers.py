@@ -19,13 +19,17 @@ CONFIGS = {
     "c2s_f32": (64, 4, 8, "f32"),
     "c3s_bf16": (64, 4, 16, "bf16"),
     "c1s_f32": (64, 3, 4, "f32"),
+    # the paper's default network (Sec. 4.1, Sec. 6): encoded input, selection output
+    "paper_bf16": (128, 4, 8, "bf16"),
 }
-SELECTION = {"c2s_f32", "c3s_bf16", "c1s_f32"}
+SELECTION = {"c2s_f32", "c3s_bf16", "c1s_f32", "paper_bf16"}
+ENCODED = {"paper_bf16"}
 
 
 def weights_for(name, seed=42, out_scale=1.0):
     H, NH, K, _ = CONFIGS[name]
-    mats = synth.init_weights(synth.layer_shapes(H, NH, K, selection=name in SELECTION), synth.rng_for(seed))
+    shapes = synth.layer_shapes(H, NH, K, selection=name in SELECTION, encoded=name in ENCODED)
+    mats = synth.init_weights(shapes, synth.rng_for(seed))
     mats[-1] = (mats[-1] * out_scale).astype(np.float32)
     return mats
 
@@ -36,6 +40,8 @@ def make_guide(name, seed=42, out_scale=1.0, max_batch=1 << 18, **kw):
     mats = weights_for(name, seed, out_scale)
     if name in SELECTION:
         kw.setdefault("selection", True)
+    if name in ENCODED:
+        kw.setdefault("encoded", True)
     g = NasgGuide(synth.flat_weights(mats), hidden=H, n_hidden=NH, n_lobes=K, precision=prec,
                   max_batch=max_batch, **kw)
     return g, mats

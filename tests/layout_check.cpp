@@ -8,8 +8,8 @@
 
 using namespace nasg;
 
-static int check_net(int H, int NH, int K, int S) {
-  NetDims d{H, NH, K, S};
+static int check_net(int H, int NH, int K, int S, int E) {
+  NetDims d{H, NH, K, S, E};
   const int64_t nw = d.num_weights();
   int bad = 0;
   // permutations are bijections
@@ -53,7 +53,7 @@ static int check_net(int H, int NH, int K, int S) {
   }
   for (int64_t i = 0; i < nw; ++i)
     if (seen[i] != 1) ++bad;
-  printf("H=%d NH=%d K=%d S=%d weights=%lld bad=%d\n", H, NH, K, S, (long long)nw, bad);
+  printf("H=%d NH=%d K=%d S=%d E=%d weights=%lld bad=%d\n", H, NH, K, S, E, (long long)nw, bad);
   return bad;
 }
 
@@ -62,6 +62,7 @@ int main() {
   for (int H : {64, 128})
     for (int NH : {1, 2, 3, 4})
       for (int K : {4, 8, 16, 32})
-        for (int S : {0, 1}) bad += check_net(H, NH, K, S);
+        for (int S : {0, 1})
+          for (int E : {0, 1}) bad += check_net(H, NH, K, S, E);
   return bad != 0;
 }

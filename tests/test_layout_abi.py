@@ -46,7 +46,8 @@ def test_library_exports_every_declared_symbol(lib):
 def _cfg(**kw):
     from paper_2303_08064_amd._lib import Config
     base = dict(hidden=64, n_hidden=4, n_lobes=16, precision=1, eps=0.0, lr=1e-3, beta1=0.9,
-                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, selection=0, mis_fraction=0.2, isotropic=0)
+                beta2=0.999, adam_eps=1e-8, max_batch=1 << 18, selection=0, mis_fraction=0.2, isotropic=0,
+                encoding=0)
     base.update(kw)
     return Config(**base)
 
@@ -103,6 +104,34 @@ def test_selection_sizes(lib):
     assert lib.nasg_packed_bytes(ctypes.byref(c)) == 2 * (1024 + 3 * 4096 + 144 * 64 + 3 * 4096 + 8192 + 16 * 64)
     c32 = _cfg(precision=0, n_lobes=8, selection=1)
     assert lib.nasg_packed_bytes(ctypes.byref(c32)) == 4 * (64 * 17 + 3 * 64 * 65 + 80 * 65)
+
+
+def test_encoded_network_sizes(lib):
+    """The paper's default network (Sec. 4.1, Sec. 6): W_0 [128][64] on the
+    encoded input, 8 lobes plus the selection output. BF16 packing: layer 0
+    as 16x16x32 fragments (64 x 128), three hidden layers forward and
+    backward, the output layer's 80 padded rows forward, its 64 lobe rows and
+    the selection tile backward; the workspace holds 80 BF16 raw-output
+    gradients per sample of a batch."""
+    from oracle import mlp
+    from paper_2303_08064_amd._lib import State, NASG_E_ARG
+    c = _cfg(hidden=128, n_lobes=8, selection=1, encoding=1, max_batch=4096)
+    nw = sum(o * i for (o, i) in mlp.layer_shapes(128, 4, 8, selection=True, encoded=True))
+    assert nw == 65664 and lib.nasg_num_weights(ctypes.byref(c)) == nw
+    H = 128
+    assert lib.nasg_packed_bytes(ctypes.byref(c)) == 2 * (64 * H + 3 * H * H + 80 * H + 3 * H * H + 64 * H + 16 * H)
+    assert lib.nasg_workspace_bytes(ctypes.byref(c)) >= 256 * nw * 4 + 4096 * 80 * 2
+    # only that combination carries the encoded input
+    for kw in (dict(hidden=64, n_lobes=8, selection=1, encoding=1),
+               dict(hidden=128, n_lobes=8, selection=1, encoding=1, precision=0),
+               dict(hidden=128, n_lobes=8, selection=0, encoding=1),
+               dict(hidden=128, n_lobes=32, selection=0, encoding=1),
+               dict(hidden=128, n_lobes=8, selection=1, encoding=0),
+               dict(hidden=128, n_lobes=8, selection=1, encoding=2)):
+        assert lib.nasg_packed_bytes(ctypes.byref(_cfg(**kw))) == 0, kw
+    ctx = ctypes.c_void_p()
+    assert lib.nasg_create(ctypes.byref(_cfg(encoding=1)), ctypes.byref(State()), ctypes.byref(ctx)) == NASG_E_ARG
+    assert b"encoded" in lib.nasg_last_error()
 
 
 def test_blend_ramp_matches_oracle(lib):
