@@ -64,7 +64,8 @@ def parse():
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-configs", action="store_true")
-    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy", "c5", "paper"], default=None,
+    p.add_argument("--only", choices=["frame", "query", "records", "train", "copy", "c5", "paper", "paper_query",
+                                      "paper_train"], default=None,
                    help="run one leg only (for profilers)")
     return p.parse_args()
 
@@ -461,6 +462,17 @@ def main():
             g.train_step(*b)
         torch.cuda.synchronize()
         print(json.dumps({"only": "c5", "steps": a.steps}))
+        return
+    if a.only in ("paper_query", "paper_train"):
+        fr = PaperFrame()
+        (f, xi), (d, p, c) = fr.q_in[0], fr.q_out[0]
+        for _ in range(a.steps):
+            if a.only == "paper_query":
+                fr.guide.query(f, xi, dir_out=d, pdf_out=p, sel_out=c)
+            else:
+                fr.guide.train_step(*fr.t_in[0][:3], bsdf_pdf=fr.t_in[0][3])
+        torch.cuda.synchronize()
+        print(json.dumps({"only": a.only, "steps": a.steps}))
         return
     if a.only == "paper":
         print(json.dumps({"only": "paper", **paper_leg(a.steps, not a.no_graph)}))

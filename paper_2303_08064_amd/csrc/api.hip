@@ -248,9 +248,9 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.sel = ctx->d.S;
   a.amul = ctx->cfg.isotropic ? 0.0f : 1.0f;
   a.num_cus = ctx->num_cus;
-  hipError_t e = is_large(&ctx->cfg)
-                     ? launch_large_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream)
-                     : launch_query(a, ctx->d.H, ctx->d.K, ctx->cfg.precision, mode, (hipStream_t)stream);
+  hipError_t e = query_is_resident(ctx->d, ctx->cfg.precision)
+                     ? launch_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream)
+                     : launch_large_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream);
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 

@@ -15,6 +15,9 @@
 // output, encoded input): K = 32 on the raw features, and the paper's default
 // network (Sec. 4.1, Sec. 6).
 #define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0) X(128, 8, 1, 1, 1)
+// Large networks whose BF16 forward weights fit in LDS (132 KiB): their
+// queries run the LDS-resident query kernel, not the weight pipeline.
+#define NASG_FOR_EACH_RESIDENT_QUERY(X) X(128, 8, 1, 1, 1)
 
 namespace nasg {
 
@@ -177,7 +180,9 @@ __device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
   return m == -INFINITY ? -INFINITY : m + flog(s);
 }
 
-hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st);
+hipError_t launch_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st);
+// the network's queries run the LDS-resident query kernel
+bool query_is_resident(const NetDims& d, int prec);
 hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_pdf_grad(const RecArgs& a, int K, hipStream_t st);

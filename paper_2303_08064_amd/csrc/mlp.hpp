@@ -161,6 +161,52 @@ struct Mlp<H, K, 1, E> {
     }
   }
 
+  // NB vertex blocks at once: each weight fragment read from LDS feeds NB
+  // MFMAs, which divides the LDS traffic per FLOP by NB
+  template <int NB>
+  __device__ static void layer0_linear_nb(const __bf16* lds, const Input (&x)[NB], float (&y)[NB][MTH][4],
+                                          int lane) {
+#pragma unroll
+    for (int mt = 0; mt < MTH; ++mt) {
+      f32x4 acc[NB];
+      if constexpr (E == 1) {
+        const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+        const bf16x8 a0 = frag[(mt * 2) * 64 + lane], a1 = frag[(mt * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_bf16_32(a1, x[nb].b[1], mfma_bf16_32(a0, x[nb].b[0], zero4()));
+      } else {
+        const bf16x4 a = reinterpret_cast<const bf16x4*>(lds)[mt * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_bf16_16(a, x[nb], zero4());
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[nb][mt][i] = acc[nb][i];
+    }
+  }
+  template <int MT, int NB>
+  __device__ static void gemm_op_nb(const __bf16* lds, const bf16x8 (&b)[NB][KBH], float (&out)[NB][MT][4],
+                                    int lane) {
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f32x4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KBH; ++kb) {
+        const bf16x8 a = frag[(mt * KBH + kb) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_bf16_32(a, b[nb][kb], acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[nb][mt][i] = acc[nb][i];
+    }
+  }
+
   // out = W in over MT row tiles from ready B operands
   template <int MT>
   __device__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
@@ -266,19 +312,19 @@ struct Mlp<H, K, 0, E> {
 // Forward through all layers; h[l] keeps hidden activations for the backward.
 // S = 1: the output layer has one more 16-row tile whose row 0 is the
 // selection logit (rows 8K .. 8K+15; the rest are zero padding).
-template <int H, int K, int PREC, int NHMAX, int S = 0>
+template <int H, int K, int PREC, int NHMAX, int S = 0, int E = 0>
 struct Forward {
-  typedef Mlp<H, K, PREC> M;
+  typedef Mlp<H, K, PREC, E> M;
   typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
   static constexpr int MTO = M::MTO + S;   // output row tiles
 
   // offsets (elements) of each layer's forward weights in LDS
   __device__ static const W* layer_ptr(const W* lds, int l, int nh) {
     if (PREC == 1) {
-      Bf16Layout Lt{NetDims{H, nh, K, S}};
+      Bf16Layout Lt{NetDims{H, nh, K, S, E}};
       return lds + Lt.fwd_off(l);
     } else {
-      F32Layout Lt{NetDims{H, nh, K, S}};
+      F32Layout Lt{NetDims{H, nh, K, S, E}};
       return lds + Lt.off(l);
     }
   }
@@ -309,6 +355,27 @@ struct Forward {
       }
     }
     M::template gemm<MTO>(layer_ptr(lds, nh, nh), last, out, lane);
+  }
+
+  // BF16 query forward of NB vertex blocks sharing every weight fragment read
+  template <int NB>
+  __device__ static void run_query_nb(const W* lds, int nh, const typename M::Input (&x)[NB],
+                                      float (&out)[NB][MTO][4], int lane) {
+    static_assert(PREC == 1, "BF16 only");
+    float y[NB][M::MTH][4];
+    bf16x8 b[NB][M::KBH];
+    M::template layer0_linear_nb<NB>(layer_ptr(lds, 0, nh), x, y, lane);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) M::relu_operands(y[nb], b[nb]);
+#pragma unroll
+    for (int l = 1; l < NHMAX; ++l) {
+      if (l < nh) {
+        M::template gemm_op_nb<M::MTH, NB>(layer_ptr(lds, l, nh), b, y, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) M::relu_operands(y[nb], b[nb]);
+      }
+    }
+    M::template gemm_op_nb<MTO, NB>(layer_ptr(lds, nh, nh), b, out, lane);
   }
 
   // Forward for queries (no activations kept): in BF16 the layers pass

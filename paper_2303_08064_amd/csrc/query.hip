@@ -13,15 +13,76 @@
 
 namespace nasg {
 
-// MODE 0: query, 1: raw forward only; S = 1: the network has the selection
-// output (row 8K, read by lane group 0 from the extra output tile)
-template <int H, int K, int PREC, int MODE, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 3 : 1))) void query_kernel(QueryArgs a) {
-  constexpr int NHMAX = 4;
+// Waves per SIMD the query kernel is compiled for: three for the hidden-64
+// networks (VALU-bound epilogue), one for their raw forward; two for the
+// hidden-128 network, whose 132 KiB of forward weights leave room for one
+// workgroup per CU.
+constexpr int query_waves_per_eu(int H, int MODE) { return H == 64 ? (MODE == 0 ? 3 : 1) : 2; }
+
+// The rest of a query for one 16-vertex block from its raw outputs: decode,
+// choose a lobe, sample, evaluate the pdf and store (MODE 0), or store the
+// raw outputs in canonical row order (MODE 1).
+template <int K, int MODE, int S, int MTO>
+__device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&out)[MTO][4], int64_t v, int g,
+                                             int c) {
   constexpr int KQ = K / 4;
-  typedef Mlp<H, K, PREC> M;
-  typedef Forward<H, K, PREC, NHMAX, S> F;
+  const bool valid = v < a.B;
+  if (MODE == 1) {
+    // accumulator t of lane group g is parameter t / KQ of lobe g*KQ + t % KQ
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 2 * K; ++t) {
+        int p = t / KQ, k = g * KQ + t % KQ;
+        a.raw_out[(int64_t)(p * K + k) * a.ld + v] = out[t >> 2][t & 3];
+      }
+      if (S == 1 && g == 0) a.raw_out[(int64_t)(8 * K) * a.ld + v] = out[MTO - 1][0];
+    }
+    return;
+  }
+  float xi_sel = 0.0f, xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
+  if (valid) {
+    xi_sel = a.xi[v];
+    xi0 = a.xi[a.ld + v];
+    xi1 = a.xi[2 * a.ld + v];
+    xi2 = a.xi[3 * a.ld + v];
+  }
+  Lobe lb[KQ];
+  float vx, vy, vz;
+  const float logq = query_epilogue<KQ, MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz, a.amul);
+
+  if (valid && g == 0) {
+    a.dir_out[v] = vx;
+    a.dir_out[a.ld + v] = vy;
+    a.dir_out[2 * a.ld + v] = vz;
+    a.pdf_out[v] = fexp(logq);
+    // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
+    if (S == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[MTO - 1][0]));
+  }
+  if (a.rec_out != nullptr && valid) {
+    float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int k = g * KQ + q;
+      const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz,
+                             lb[q].lam, lb[q].a, lb[q].logc};
+#pragma unroll
+      for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
+    }
+  }
+}
+
+// MODE 0: query, 1: raw forward only; S = 1: the network has the selection
+// output (row 8K, read by lane group 0 from the extra output tile); E = 1:
+// the encoded input; NB: 16-vertex blocks per wave per pass (NB > 1 shares
+// every weight fragment read among NB MFMAs); NW: waves per workgroup.
+template <int H, int K, int PREC, int MODE, int S, int E, int NB, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(query_waves_per_eu(H, MODE))))
+void query_kernel(QueryArgs a) {
+  constexpr int NHMAX = 4;
+  typedef Mlp<H, K, PREC, E> M;
+  typedef Forward<H, K, PREC, NHMAX, S, E> F;
   typedef typename F::W W;
+  static_assert(NB == 1 || PREC == 1, "multi-block passes are BF16 only");
   extern __shared__ __align__(16) unsigned char smem[];
   W* lds = reinterpret_cast<W*>(smem);
   block_copy_to_lds(lds, a.wpack, a.lds_bytes);
@@ -31,65 +92,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ?
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
-  const int64_t n_tiles = (a.B + kTileV - 1) / kTileV;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t v = tile * kTileV + c;
-    const bool valid = v < a.B;
-    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
-    float out[F::MTO][4];
-    F::run_query(wts, a.nh, x, out, lane);
-
-    if (MODE == 1) {
-      // raw outputs in canonical row order: accumulator t of lane group g is
-      // parameter t / KQ of lobe g*KQ + t % KQ
-      if (valid) {
+  constexpr int TV = kTileV * NB;   // vertices per wave pass
+  const int64_t n_tiles = (a.B + TV - 1) / TV;
+  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += (int64_t)gridDim.x * NW) {
+    if constexpr (NB == 1) {
+      const int64_t v = tile * kTileV + c;
+      typename M::Input x = M::load_input(a.feat, a.ld, v, v < a.B, g);
+      float out[F::MTO][4];
+      F::run_query(wts, a.nh, x, out, lane);
+      finish_block<K, MODE, S>(a, out, v, g, c);
+    } else {
+      typename M::Input x[NB];
 #pragma unroll
-        for (int t = 0; t < 2 * K; ++t) {
-          int p = t / KQ, k = g * KQ + t % KQ;
-          a.raw_out[(int64_t)(p * K + k) * a.ld + v] = out[t >> 2][t & 3];
-        }
-        if (S == 1 && g == 0) a.raw_out[(int64_t)(8 * K) * a.ld + v] = out[F::MTO - 1][0];
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t v = tile * TV + nb * kTileV + c;
+        x[nb] = M::load_input(a.feat, a.ld, v, v < a.B, g);
       }
-      continue;
-    }
-
-    float xi_sel = 0.0f, xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
-    if (valid) {
-      xi_sel = a.xi[v];
-      xi0 = a.xi[a.ld + v];
-      xi1 = a.xi[2 * a.ld + v];
-      xi2 = a.xi[3 * a.ld + v];
-    }
-    Lobe lb[KQ];
-    float vx, vy, vz;
-    const float logq =
-        query_epilogue<KQ, F::MTO>(out, xi_sel, xi0, xi1, xi2, a.eps, g, c, lb, vx, vy, vz, a.amul);
-
-    if (valid && g == 0) {
-      a.dir_out[v] = vx;
-      a.dir_out[a.ld + v] = vy;
-      a.dir_out[2 * a.ld + v] = vz;
-      a.pdf_out[v] = fexp(logq);
-      // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
-      if (S == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[F::MTO - 1][0]));
-    }
-    if (a.rec_out != nullptr && valid) {
-      float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+      float out[NB][F::MTO][4];
+      F::template run_query_nb<NB>(wts, a.nh, x, out, lane);
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) {
-        const int k = g * KQ + q;
-        const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz,
-                               lb[q].lam, lb[q].a, lb[q].logc};
-#pragma unroll
-        for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
-      }
+      for (int nb = 0; nb < NB; ++nb) finish_block<K, MODE, S>(a, out[nb], tile * TV + nb * kTileV + c, g, c);
     }
   }
 }
 
-template <int H, int K, int PREC, int S>
+template <int H, int K, int PREC, int S, int E, int NB, int NW>
 static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
-  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S> : query_kernel<H, K, PREC, 1, S>;
+  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S, E, NB, NW> : query_kernel<H, K, PREC, 1, S, E, NB, NW>;
+  constexpr int threads = 64 * NW;
   // occupancy depends on the LDS footprint; cache it per (mode, footprint)
   static int cached_bytes[2] = {-1, -1};
   static int cached_per_cu[2] = {1, 1};
@@ -97,31 +127,50 @@ static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, a.lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, a.lds_bytes);
     if (e != hipSuccess) return e;
     cached_per_cu[mode] = per_cu < 1 ? 1 : per_cu;
     cached_bytes[mode] = a.lds_bytes;
   }
-  const int64_t n_tiles = (a.B + kTileV - 1) / kTileV;
-  const int64_t want = (n_tiles + 3) / 4;
+  const int64_t n_tiles = (a.B + kTileV * NB - 1) / (kTileV * NB);
+  const int64_t want = (n_tiles + NW - 1) / NW;
   const int64_t cap = (int64_t)cached_per_cu[mode] * a.num_cus;
   int grid = (int)(want < cap ? want : cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), a.lds_bytes, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), a.lds_bytes, st, a);
   return hipGetLastError();
 }
 
 template <int H, int K, int PREC>
 static hipError_t launch_query_t(const QueryArgs& a, int mode, hipStream_t st) {
-  return a.sel ? launch_query_s<H, K, PREC, 1>(a, mode, st) : launch_query_s<H, K, PREC, 0>(a, mode, st);
+  return a.sel ? launch_query_s<H, K, PREC, 1, 0, 1, 4>(a, mode, st) : launch_query_s<H, K, PREC, 0, 0, 1, 4>(a, mode, st);
 }
 
-hipError_t launch_query(const QueryArgs& a, int H, int K, int prec, int mode, hipStream_t st) {
+hipError_t launch_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st) {
 #define NASG_CASE(h, k, p) \
-  if (H == h && K == k && prec == p) return launch_query_t<h, k, p>(a, mode, st);
+  if (d.H == h && d.K == k && prec == p && d.E == 0) return launch_query_t<h, k, p>(a, mode, st);
   NASG_FOR_EACH_NET(NASG_CASE)
 #undef NASG_CASE
+  // hidden-128 networks whose BF16 forward weights fit in LDS: two vertex
+  // blocks per wave, eight waves per workgroup
+#define NASG_CASE(h, k, p, s, e)                                          \
+  if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) \
+    return launch_query_s<h, k, p, s, e, 2, 8>(a, mode, st);
+  NASG_FOR_EACH_RESIDENT_QUERY(NASG_CASE)
+#undef NASG_CASE
   return hipErrorInvalidValue;
+}
+
+bool query_is_resident(const NetDims& d, int prec) {
+#define NASG_CASE(h, k, p) \
+  if (d.H == h && d.K == k && prec == p && d.E == 0) return true;
+  NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+#define NASG_CASE(h, k, p, s, e) \
+  if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) return true;
+  NASG_FOR_EACH_RESIDENT_QUERY(NASG_CASE)
+#undef NASG_CASE
+  return false;
 }
 
 }  // namespace nasg
