@@ -391,6 +391,7 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
     la.loss_partial = t.loss_partial;
     la.n_weights = t.n_weights;
     la.amul = t.amul;
+    la.num_cus = ctx->num_cus;
     e = launch_large_train(la, ctx->d, ctx->cfg.precision, n_wg, n_loss, (hipStream_t)stream);
   } else {
     e = launch_train(t, ctx->d.H, ctx->d.K, ctx->cfg.precision, n_wg, (hipStream_t)stream);

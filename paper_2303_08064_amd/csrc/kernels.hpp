@@ -84,6 +84,7 @@ struct LargeTrainArgs {
   double* loss_partial;  // [n_grad][2] (gradient kernel's grid)
   int64_t n_weights;
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
+  int num_cus;
 };
 
 struct ReduceArgs {

@@ -573,9 +573,12 @@ constexpr int kBwdWaves = 8;
 constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
 constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
 
-template <int H, int K, int SEL, int ENC, int GROUP>
-__global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void bwd_bf16_kernel(LargeTrainArgs a) {
+// One workgroup's share of a backward group: tiles wg, wg + n_wg, ... OWN
+// (group 0 only): evaluate the loss gradient itself (the forward's output
+// layer and the epilogue) instead of reading group 1's stored one, so that
+// the two groups can run at the same time.
+template <int H, int K, int SEL, int ENC, int GROUP, bool OWN>
+__device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, int n_wg) {
   typedef NetBf16<H, K, SEL, ENC> N;
   typedef typename N::M M;
   typedef __bf16 W;
@@ -626,7 +629,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
   W* b1 = bufB;
   N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  for (int64_t tile = wgi; tile < n_tiles; tile += n_wg) {
     const int64_t v = tile * kBwdV + wave * 16 + c;
     const int64_t blk = tile * kBwdWaves + wave;   // this wave's 16-vertex block
     const bool valid = v < a.B;
@@ -634,7 +637,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
     Pk<MTH> hp[NH];
     bf16x8 bo[KBO];
     bf16x4 bs = {};
-    if constexpr (GROUP == 1) {
+    if constexpr (GROUP == 1 || OWN) {
       float vx = 0.0f, vy = 0.0f, vz = 1.0f, wj = 0.0f, pfs = 0.0f;
       if (valid) {
         vx = a.dir[v]; vy = a.dir[a.ld + v]; vz = a.dir[2 * a.ld + v];
@@ -650,7 +653,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
       float dl[MTO][4];
       const float lterm =
           train_epilogue<N::KQ, MTO, SEL>(out, vx, vy, vz, gs, valid, a.eps, dl, pfs, a.mis_e, a.amul);
-      if (valid && g == 0) {
+      if (GROUP == 1 && valid && g == 0) {
         loss_sum += (double)wj * (double)(-lterm);
         w_sum += (double)wj;
       }
@@ -662,7 +665,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[MTO - 1][j];
       }
-      DO::store_operands(a.dout, blk, bo, bs, lane);
+      if constexpr (GROUP == 1) DO::store_operands(a.dout, blk, bo, bs, lane);
     } else {
       N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_STAGE, lane);   // leaves output-dgrad stage 0 in b0
       DO::load_operands(a.dout, blk, bo, bs, lane);
@@ -746,7 +749,7 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
     }
   }
 
-  float* part = a.partial + (int64_t)blockIdx.x * a.n_weights;
+  float* part = a.partial + (int64_t)wgi * a.n_weights;
   if constexpr (GROUP == 0) {
     flush_tiles<1, CTH>(part, dims, NH, rt, n_out_rt, accO[0], lane);
     if constexpr (N::NOUT == 2) flush_tiles<1, CTH>(part, dims, NH, rt_hi, 1, accO[N::NOUT - 1], lane);
@@ -768,9 +771,24 @@ void bwd_bf16_kernel(LargeTrainArgs a) {
       double ls = 0.0, ws = 0.0;
 #pragma unroll
       for (int w = 0; w < kBwdWaves; ++w) { ls += red[w][0]; ws += red[w][1]; }
-      a.loss_partial[2 * blockIdx.x] = ls;
-      a.loss_partial[2 * blockIdx.x + 1] = ws;
+      a.loss_partial[2 * wgi] = ls;
+      a.loss_partial[2 * wgi + 1] = ws;
     }
+  }
+}
+
+// GROUP 0 or 1: that group over the whole grid. GROUP 2 (small batches, when
+// both groups fit on the GPU at once): group 1 on the first half of the
+// grid and group 0, evaluating the loss gradient itself, on the second half.
+template <int H, int K, int SEL, int ENC, int GROUP>
+__global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bwd_bf16_kernel(LargeTrainArgs a) {
+  if constexpr (GROUP == 2) {
+    const int half = (int)(gridDim.x >> 1);
+    if ((int)blockIdx.x < half) bwd_bf16_body<H, K, SEL, ENC, 1, false>(a, (int)blockIdx.x, half);
+    else bwd_bf16_body<H, K, SEL, ENC, 0, true>(a, (int)blockIdx.x - half, half);
+  } else {
+    bwd_bf16_body<H, K, SEL, ENC, GROUP, false>(a, (int)blockIdx.x, (int)gridDim.x);
   }
 }
 
@@ -954,15 +972,24 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
   if constexpr (PREC == 1) {
     auto k_bwd0 = bwd_bf16_kernel<H, K, SEL, ENC, 0>;
     auto k_bwd1 = bwd_bf16_kernel<H, K, SEL, ENC, 1>;
+    auto k_both = bwd_bf16_kernel<H, K, SEL, ENC, 2>;
     if (!attr) {
       hipError_t e = set_lds(k_bwd0, Lds::bwd);
       if (e == hipSuccess) e = set_lds(k_bwd1, Lds::bwd);
+      if (e == hipSuccess) e = set_lds(k_both, Lds::bwd);
       if (e != hipSuccess) return e;
       attr = true;
     }
-    // the group-1 kernel computes and stores the raw-output gradient first
-    hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
-    hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+    if (2 * n_wg <= a.num_cus) {
+      // a small batch: one workgroup per CU for both groups at once (group 0
+      // repeats the output layer and the NASG gradient instead of waiting
+      // for group 1's)
+      hipLaunchKernelGGL(k_both, dim3(2 * n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+    } else {
+      // the group-1 kernel computes and stores the raw-output gradient first
+      hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+      hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
+    }
   } else {
     auto k_grad = gradout_kernel<H, K>;
     auto k_bwd0 = bwd_f32_kernel<H, K, 0>;

@@ -100,9 +100,12 @@ def test_encoding_reaches_the_network():
         _check_raw(raw, omlp.forward(W, f.T, bf16=True).numpy())
 
 
-@pytest.mark.parametrize("B", [100, 4096 + 35])
+@pytest.mark.parametrize("B", [100, 4096 + 35, 20000])
 def test_blended_loss_grad(B):
-    g, mats = make_guide(NAME, out_scale=2.0, mis_fraction=E, max_batch=8192)
+    """Up to 16384 samples (on 256 CUs) both backward groups run at once,
+    group 0 evaluating the loss gradient itself; above that, one after the
+    other through the stored gradient. Both schedules are checked."""
+    g, mats = make_guide(NAME, out_scale=2.0, mis_fraction=E, max_batch=B)
     feat, dirs, w, pdf = _batch(B, 63)
     g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
     torch.cuda.synchronize()
