@@ -240,6 +240,26 @@ struct NetBf16 {
     output(wg, b0, b1, hp[NH - 1], out, wg + Lt.fwd_off(0), L0, lane);
   }
 
+  // Forward of one tile with every forward weight resident at `base` in the
+  // packed forward order (FWD elements): no stage waits.
+  static constexpr int FWD = L0 + (NH - 1) * H * H + OUT;
+  __device__ static void forward_resident(const W* base, const typename M::Input& x, Pk<MTH> (&hp)[NH],
+                                          float (&out)[MTO][4], int lane) {
+    const Bf16Layout Lt = layout();
+    float y[MTH][4];
+    bf16x8 b[M::KBH];
+    M::layer0_linear(base, x, y, lane);
+    M::relu_operands(y, b);
+    hp[0].from_ops(b);
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      M::template gemm_op<MTH>(base + Lt.fwd_off(l), b, y, lane);
+      M::relu_operands(y, b);
+      hp[l].from_ops(b);
+    }
+    M::template gemm_op<MTO>(base + Lt.fwd_off(NH), b, out, lane);
+  }
+
   // dh = W_out^T dl with the output layer's first backward stage resident in
   // b0: bo holds dl's 8K lobe rows as B operands, bs the selection tile's.
   // `next` (elems) is resident in b0 on return.
@@ -573,13 +593,33 @@ constexpr int kBwdWaves = 8;
 constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
 constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
 
+// LDS of the weight buffers, and of the backward kernels (weights + staging)
+template <int H, int K, int PREC, int SEL, int ENC>
+struct LargeLds {
+  typedef LargeNet<H, K, PREC, SEL, ENC> N;
+  static constexpr size_t fwd = (size_t)(PREC == 1 ? 2 : 1) * N::BUF * sizeof(typename N::W);
+  static constexpr size_t bwd = PREC == 1 ? fwd + (size_t)2 * H * kBwdSP * sizeof(__bf16)
+                                          : fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
+  static constexpr int bwd_threads = PREC == 1 ? 64 * kBwdWaves : 256;
+  static_assert(bwd <= 160 * 1024, "LDS budget");
+  static_assert(PREC == 1 || (SEL == 0 && ENC == 0), "the FP32 network has neither option");
+};
+
+
 // One workgroup's share of a backward group: tiles wg, wg + n_wg, ... OWN
 // (group 0 only): evaluate the loss gradient itself (the forward's output
 // layer and the epilogue) instead of reading group 1's stored one, so that
 // the two groups can run at the same time.
-template <int H, int K, int SEL, int ENC, int GROUP, bool OWN>
+// SINGLE: the workgroup has one tile at most, so the tile loop has no back
+// edge and the gradient accumulators are live from their first MFMA only
+// (not across the forward and the epilogue). RES (SINGLE, loss gradient
+// evaluated here): the whole forward image is loaded at once into the LDS
+// (the two weight buffers and the staging area, which the forward does not
+// use), so the forward waits for memory once instead of once per layer.
+template <int H, int K, int SEL, int ENC, int GROUP, bool OWN, bool SINGLE = false, bool RES = false>
 __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, int n_wg) {
   typedef NetBf16<H, K, SEL, ENC> N;
+  static_assert(!RES || (SINGLE && (GROUP == 1 || OWN)), "the resident forward: one tile, loss gradient here");
   typedef typename N::M M;
   typedef __bf16 W;
   typedef __bf16 St;   // staging element
@@ -627,7 +667,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
   double loss_sum = 0.0, w_sum = 0.0;
   W* b0 = bufA;
   W* b1 = bufB;
-  N::begin(wg, b0);
+  if constexpr (!RES) N::begin(wg, b0);
   const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
   for (int64_t tile = wgi; tile < n_tiles; tile += n_wg) {
     const int64_t v = tile * kBwdV + wave * 16 + c;
@@ -644,9 +684,18 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         wj = a.w[v];
         if constexpr (SEL == 1) pfs = a.bsdf_pdf[v];
       }
-      N::hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), N::OUT_STAGE, lane);    // output stage 0 -> b0
       float out[MTO][4];
-      N::output(wg, b0, b1, hp[NH - 1], out, out_bwd, N::OB_STAGE, lane);      // output-dgrad stage 0 -> b0
+      if constexpr (RES) {
+        __syncthreads();                                                        // a previous tile's staging is read
+        N::dma(bufA, wg, N::FWD);
+        N::sync_stage();
+        N::forward_resident(bufA, x, hp, out, lane);
+        __syncthreads();                                                        // the forward image is consumed
+        N::dma(b0, out_bwd, N::OB_STAGE);                                       // awaited after the epilogue
+      } else {
+        N::hidden(wg, b0, b1, x, hp, wg + Lt.fwd_off(NH), N::OUT_STAGE, lane);  // output stage 0 -> b0
+        N::output(wg, b0, b1, hp[NH - 1], out, out_bwd, N::OB_STAGE, lane);    // output-dgrad stage 0 -> b0
+      }
       const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
       vx *= inv; vy *= inv; vz *= inv;
       const float gs = valid ? -wj * inv_b : 0.0f;
@@ -666,6 +715,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[MTO - 1][j];
       }
       if constexpr (GROUP == 1) DO::store_operands(a.dout, blk, bo, bs, lane);
+      if constexpr (RES) N::sync_stage();                                       // output-dgrad stage 0 in b0
     } else {
       N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_STAGE, lane);   // leaves output-dgrad stage 0 in b0
       DO::load_operands(a.dout, blk, bo, bs, lane);
@@ -692,7 +742,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[N::NOUT - 1], lane);
       } else {
         dlw.template stage<SP, 0, MTO>(dst, wave, lane);            // every output row
-        N::dma(b1, wg + Lt.fwd_off(0), N::L0);                      // the next tile's layer 0
+        if constexpr (!RES) N::dma(b1, wg + Lt.fwd_off(0), N::L0);  // the next tile's layer 0
         dgrad_rows<KBO, MTH, 0>(b0, bo, dh, lane);
         if constexpr (SEL == 1) dgrad_sel(b0 + 8 * K * H, bs, dh, lane);
         N::sync_stage();                                            // also publishes the staging
@@ -727,7 +777,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         d2w.template stage<SP>(dst, wave, lane);
         hp[l - 1].template stage<SP>(hst, wave, lane);
         if (l > 1) N::dma(oth, wg + Lt.bwd_off(l - 1), H * H);
-        else N::dma(oth, wg + Lt.fwd_off(0), N::L0);              // the next tile's layer 0
+        else if (!RES) N::dma(oth, wg + Lt.fwd_off(0), N::L0);    // the next tile's layer 0
         bf16x8 op[KBH];
         d2w.ops(op);
         float dn[MTH][4];
@@ -747,6 +797,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
       b0 = cur;   // the next tile's layer 0
       b1 = oth;
     }
+    if constexpr (SINGLE) break;
   }
 
   float* part = a.partial + (int64_t)wgi * a.n_weights;
@@ -778,15 +829,18 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
 }
 
 // GROUP 0 or 1: that group over the whole grid. GROUP 2 (small batches, when
-// both groups fit on the GPU at once): group 1 on the first half of the
-// grid and group 0, evaluating the loss gradient itself, on the second half.
+// both groups fit on the GPU at once, one tile per workgroup): group 1 on the
+// first half of the grid and group 0, evaluating the loss gradient itself,
+// on the second half.
 template <int H, int K, int SEL, int ENC, int GROUP>
 __global__ __launch_bounds__(64 * kBwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bwd_bf16_kernel(LargeTrainArgs a) {
   if constexpr (GROUP == 2) {
+    // one tile per workgroup here; the forward image fits the LDS for K = 8
+    constexpr bool RES = NetBf16<H, K, SEL, ENC>::FWD <= LargeLds<H, K, 1, SEL, ENC>::bwd / 2;
     const int half = (int)(gridDim.x >> 1);
-    if ((int)blockIdx.x < half) bwd_bf16_body<H, K, SEL, ENC, 1, false>(a, (int)blockIdx.x, half);
-    else bwd_bf16_body<H, K, SEL, ENC, 0, true>(a, (int)blockIdx.x - half, half);
+    if ((int)blockIdx.x < half) bwd_bf16_body<H, K, SEL, ENC, 1, false, true, RES>(a, (int)blockIdx.x, half);
+    else bwd_bf16_body<H, K, SEL, ENC, 0, true, true, RES>(a, (int)blockIdx.x - half, half);
   } else {
     bwd_bf16_body<H, K, SEL, ENC, GROUP, false>(a, (int)blockIdx.x, (int)gridDim.x);
   }
@@ -913,18 +967,6 @@ static hipError_t set_lds(Kern kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// LDS of the weight buffers, and of the backward kernels (weights + staging)
-template <int H, int K, int PREC, int SEL, int ENC>
-struct LargeLds {
-  typedef LargeNet<H, K, PREC, SEL, ENC> N;
-  static constexpr size_t fwd = (size_t)(PREC == 1 ? 2 : 1) * N::BUF * sizeof(typename N::W);
-  static constexpr size_t bwd = PREC == 1 ? fwd + (size_t)2 * H * kBwdSP * sizeof(__bf16)
-                                          : fwd + (size_t)(N::RMAX + H) * N::SP * sizeof(typename N::W);
-  static constexpr int bwd_threads = PREC == 1 ? 64 * kBwdWaves : 256;
-  static_assert(bwd <= 160 * 1024, "LDS budget");
-  static_assert(PREC == 1 || (SEL == 0 && ENC == 0), "the FP32 network has neither option");
-};
-
 template <int H, int K, int PREC, int SEL, int ENC>
 static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t st) {
   const size_t shmem = LargeLds<H, K, PREC, SEL, ENC>::fwd;
@@ -980,10 +1022,11 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
       if (e != hipSuccess) return e;
       attr = true;
     }
-    if (2 * n_wg <= a.num_cus) {
-      // a small batch: one workgroup per CU for both groups at once (group 0
-      // repeats the output layer and the NASG gradient instead of waiting
-      // for group 1's)
+    const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
+    if (n_tiles <= n_wg && 2 * n_wg <= a.num_cus) {
+      // a small batch: one tile per workgroup and one workgroup per CU for
+      // both groups at once (group 0 repeats the output layer and the NASG
+      // gradient instead of waiting for group 1's)
       hipLaunchKernelGGL(k_both, dim3(2 * n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
     } else {
       // the group-1 kernel computes and stores the raw-output gradient first
