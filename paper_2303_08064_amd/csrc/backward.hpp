@@ -209,7 +209,8 @@ __device__ __forceinline__ void flush_own(float* part, const NetDims& d, int l,
 }
 
 // Flush a wave's dW tiles of layer l to the workgroup's canonical partial.
-template <int NR, int NC>
+// PAD: the tiles may hold the selection tile's padding rows (skipped).
+template <int NR, int NC, bool PAD = false>
 __device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l, const int (&rt)[NR], int nrt,
                                             const f32x4 (&acc)[NR][NC], int lane) {
   const int g = lane >> 4, c = lane & 15;
@@ -226,7 +227,7 @@ __device__ __forceinline__ void flush_tiles(float* part, const NetDims& d, int l
       for (int i = 0; i < 4; ++i) {
         const int R = rt[r] * 16 + 4 * g + i;
         const int n = (l == d.NH) ? canon_out_row(R, d.K) : R;
-        if (n >= 0) part[off + (int64_t)n * cols + k] = acc[r][ct][i];   // n < 0: padding rows
+        if (!PAD || n >= 0) part[off + (int64_t)n * cols + k] = acc[r][ct][i];   // n < 0: padding rows
       }
     }
   }

@@ -16,8 +16,10 @@
 // network (Sec. 4.1, Sec. 6).
 #define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0) X(128, 8, 1, 1, 1)
 // Large networks whose BF16 forward weights fit in LDS (132 KiB): their
-// queries run the LDS-resident query kernel, not the weight pipeline.
+// queries run the LDS-resident query kernel; the others' queries stream
+// their weights through the pipeline.
 #define NASG_FOR_EACH_RESIDENT_QUERY(X) X(128, 8, 1, 1, 1)
+#define NASG_FOR_EACH_STREAMED_QUERY(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0)
 
 namespace nasg {
 

@@ -802,7 +802,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
 
   float* part = a.partial + (int64_t)wgi * a.n_weights;
   if constexpr (GROUP == 0) {
-    flush_tiles<1, CTH>(part, dims, NH, rt, n_out_rt, accO[0], lane);
+    flush_tiles<1, CTH, SEL == 1>(part, dims, NH, rt, n_out_rt, accO[0], lane);
     if constexpr (N::NOUT == 2) flush_tiles<1, CTH>(part, dims, NH, rt_hi, 1, accO[N::NOUT - 1], lane);
     flush_tiles<1, CTH>(part, dims, NH - 1, rt, 1, accT, lane);
   } else {
@@ -1054,7 +1054,7 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
 hipError_t launch_large_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st) {
 #define NASG_CASE(h, k, p, s, e) \
   if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) return launch_large_query_t<h, k, p, s, e>(a, mode, st);
-  NASG_FOR_EACH_LARGE_NET(NASG_CASE)
+  NASG_FOR_EACH_STREAMED_QUERY(NASG_CASE)
 #undef NASG_CASE
   return hipErrorInvalidValue;
 }

@@ -372,9 +372,26 @@ __device__ __forceinline__ void write_packed(const AdamArgs& a, const NetDims& d
 
 // Kingma and Ba's Adam, bias-corrected, no weight decay; skipped (weights,
 // moments and step unchanged, flag bit 0 set) if the loss or the gradient norm
-// is not finite.
+// is not finite. A thread's first element is loaded before the gradient norm
+// is summed, so the two memory latencies overlap; the bias corrections are
+// computed once per block, by two threads, during the norm sum.
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   __shared__ double red[256];
+  __shared__ float corr[2];
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  float g0 = 0.0f, m0 = 0.0f, v0 = 0.0f, w0 = 0.0f;
+  if (i0 < a.n_weights) {
+    g0 = a.grad[i0];
+    m0 = a.m[i0];
+    v0 = a.v[i0];
+    w0 = a.w[i0];
+  }
+  const int64_t t0 = *a.step_snapshot;
+  // bias corrections of step t0 + 1 (used only if the step is taken),
+  // computed while the other threads sum the norm partials
+  if (threadIdx.x == 0) corr[0] = a.lr / (float)(1.0 - pow((double)a.beta1, (double)(t0 + 1)));   // lr / (1 - beta1^t)
+  if (threadIdx.x == 64) corr[1] = (float)sqrt(1.0 - pow((double)a.beta2, (double)(t0 + 1)));     // sqrt(1 - beta2^t)
   double s = 0.0;
   for (int j = threadIdx.x; j < a.n_norm; j += 256) s += a.norm_partial[j];
   red[threadIdx.x] = s;
@@ -386,24 +403,25 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const double nsq = red[0];
   const double loss = a.stats[0];
   const bool skip = !isfinite(loss) || !isfinite(nsq);
-  const int64_t t0 = *a.step_snapshot;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.stats[2] = sqrt(nsq);
     *a.flags = skip ? 1u : 0u;
     *a.step = skip ? t0 : t0 + 1;
   }
   if (skip) return;
-  const double t = (double)(t0 + 1);
-  const float bc1 = (float)(1.0 - pow((double)a.beta1, t));
-  const float bc2_sqrt = (float)sqrt(1.0 - pow((double)a.beta2, t));
-  const float step_size = a.lr / bc1;
+  const float step_size = corr[0], bc2_sqrt = corr[1];
   const NetDims d{a.H, a.NH, a.K, a.S, a.E};
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n_weights; i += (int64_t)gridDim.x * 256) {
-    const float gi = a.grad[i];
-    const float m = fmaf(a.beta1, a.m[i], (1.0f - a.beta1) * gi);
-    const float v = fmaf(a.beta2, a.v[i], (1.0f - a.beta2) * gi * gi);
+  for (int64_t i = i0; i < a.n_weights; i += stride) {
+    if (i != i0) {
+      g0 = a.grad[i];
+      m0 = a.m[i];
+      v0 = a.v[i];
+      w0 = a.w[i];
+    }
+    const float m = fmaf(a.beta1, m0, (1.0f - a.beta1) * g0);
+    const float v = fmaf(a.beta2, v0, (1.0f - a.beta2) * g0 * g0);
     const float denom = sqrtf(v) / bc2_sqrt + a.adam_eps;
-    const float w = a.w[i] - step_size * (m / denom);
+    const float w = w0 - step_size * (m / denom);
     a.m[i] = m;
     a.v[i] = v;
     a.w[i] = w;
