@@ -56,7 +56,7 @@ enum { NASG_F32 = 0, NASG_BF16 = 1 };
  * without the selection output); hidden 128 with n_lobes 32 (raw features, no
  * selection output); each in FP32 or BF16; and the paper's default network
  * (Sec. 4.1, Sec. 6): hidden 128, n_lobes 8, the selection output and the
- * encoded input, in BF16. Hidden-128 networks have n_hidden = 4. */
+ * encoded input, in FP32 or BF16. Hidden-128 networks have n_hidden = 4. */
 typedef struct {
   int32_t hidden;      /* 64 or 128 (see the compiled networks above) */
   int32_t n_hidden;    /* number of hidden layers, 1..4 */

@@ -14,14 +14,15 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnasg.so")
-SOURCES = ["query.hip", "records.hip", "train.hip", "large.hip", "api.hip"]
+SOURCES = ["query.hip", "records.hip", "train.hip", "large.hip", "large_paper.hip", "api.hip"]
 # per-file code generation options: the query kernels and the large network's
 # kernels keep MFMA accumulators in VGPRs (no accumulator-register reads in
 # their VALU-bound epilogues; the large backward kernels run two waves per
 # SIMD, which leaves no accumulator registers anyway); the fused training
 # kernel needs the accumulator registers for its gradient tiles
 EXTRA = {"query.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
-         "large.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+         "large.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "large_paper.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = os.environ.get("NASG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -66,7 +66,7 @@ const char* config_error(const nasg_config* c) {
     return "unsupported network; compiled: hidden 64 with n_lobes 4, 8 or 16 on the raw features, with or "
            "without the selection output; hidden 128 with n_lobes 32 on the raw features without it; each in "
            "FP32 or BF16; and the paper's network, hidden 128 with n_lobes 8, the selection output and the "
-           "encoded input, in BF16";
+           "encoded input, in FP32 or BF16";
   if (is_large(c) && c->n_hidden != 4) return "hidden 128 networks are compiled for n_hidden = 4";
   if (!(c->mis_fraction >= 0.0f && c->mis_fraction <= 1.0f)) return "mis_fraction must be in [0, 1]";
   if (c->isotropic != 0 && c->isotropic != 1) return "isotropic must be 0 or 1";

@@ -138,8 +138,8 @@ struct Own {
   static constexpr int STEP = ROW ? NW : NW / CT;
   static constexpr int NRW = (RT + STEP - 1) / STEP;        // row tiles per wave
   static constexpr int TPW = ROW ? NRW * CT : NRW;          // tiles per wave
-  __device__ static int rt(int wave, int j) { return ROW ? wave + NW * (j / CT) : wave / CT + STEP * j; }
-  __device__ static int ct(int wave, int j) { return ROW ? j % CT : wave % CT; }
+  __device__ __forceinline__ static int rt(int wave, int j) { return ROW ? wave + NW * (j / CT) : wave / CT + STEP * j; }
+  __device__ __forceinline__ static int ct(int wave, int j) { return ROW ? j % CT : wave % CT; }
 };
 
 template <int PREC, typename S, int SP>

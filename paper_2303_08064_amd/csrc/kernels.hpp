@@ -14,12 +14,16 @@
 // NASG-gradient and backward kernels. (hidden, lobes, precision, selection
 // output, encoded input): K = 32 on the raw features, and the paper's default
 // network (Sec. 4.1, Sec. 6).
-#define NASG_FOR_EACH_LARGE_NET(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0) X(128, 8, 1, 1, 1)
+// The two groups are compiled in translation units of their own.
+#define NASG_FOR_EACH_LARGE_NET_K32(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0)
+#define NASG_FOR_EACH_LARGE_NET_PAPER(X) X(128, 8, 0, 1, 1) X(128, 8, 1, 1, 1)
+#define NASG_FOR_EACH_LARGE_NET(X) NASG_FOR_EACH_LARGE_NET_K32(X) NASG_FOR_EACH_LARGE_NET_PAPER(X)
 // Large networks whose BF16 forward weights fit in LDS (132 KiB): their
 // queries run the LDS-resident query kernel; the others' queries stream
 // their weights through the pipeline.
 #define NASG_FOR_EACH_RESIDENT_QUERY(X) X(128, 8, 1, 1, 1)
-#define NASG_FOR_EACH_STREAMED_QUERY(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0)
+#define NASG_FOR_EACH_STREAMED_QUERY_K32(X) X(128, 32, 0, 0, 0) X(128, 32, 1, 0, 0)
+#define NASG_FOR_EACH_STREAMED_QUERY_PAPER(X) X(128, 8, 0, 1, 1)
 
 namespace nasg {
 
@@ -193,6 +197,14 @@ hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hi
 hipError_t launch_large_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st);
 hipError_t launch_large_train(const LargeTrainArgs& a, const NetDims& d, int prec, int n_wg, int n_grad,
                               hipStream_t st);
+// per translation unit: true when the network is one of its own
+bool launch_large_query_k32(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st, hipError_t* err);
+bool launch_large_query_paper(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st,
+                              hipError_t* err);
+bool launch_large_train_k32(const LargeTrainArgs& a, const NetDims& d, int prec, int n_wg, int n_grad, hipStream_t st,
+                            hipError_t* err);
+bool launch_large_train_paper(const LargeTrainArgs& a, const NetDims& d, int prec, int n_wg, int n_grad,
+                              hipStream_t st, hipError_t* err);
 hipError_t launch_reduce(const ReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 hipError_t launch_pack(const float* w, void* wpack, const NetDims& d, int prec, hipStream_t st);

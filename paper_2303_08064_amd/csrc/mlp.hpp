@@ -70,11 +70,11 @@ struct Mlp<H, K, 1, E> {
 
   // features 4g..4g+3 of vertex v: p, omega_o, n, then the constant one, then
   // zeros; or the encoded input
-  __device__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+  __device__ __forceinline__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
     if constexpr (E == 1) return load_encoded(feat, ld, v, valid, g);
     else return load_raw(feat, ld, v, valid, g);
   }
-  __device__ static bf16x4 load_raw(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+  __device__ __forceinline__ static bf16x4 load_raw(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
     float f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -93,7 +93,7 @@ struct Mlp<H, K, 1, E> {
   // [row][vertex] staging buffer at vertex column wave*16: rows 4g..4g+3, or
   // for the encoded input rows kb*32 + 8g .. + 7
   template <typename S, int SP>
-  __device__ static void stage_input(S* st, const Input& x, int wave, int lane) {
+  __device__ __forceinline__ static void stage_input(S* st, const Input& x, int wave, int lane) {
     const int g = lane >> 4, c = lane & 15;
     if constexpr (E == 1) {
 #pragma unroll
@@ -106,7 +106,7 @@ struct Mlp<H, K, 1, E> {
     }
   }
 
-  __device__ static bf16x8 operand(const float (&in)[2][4]) {
+  __device__ __forceinline__ static bf16x8 operand(const float (&in)[2][4]) {
     bf16x8 b;
 #pragma unroll
     for (int j = 0; j < 8; ++j) b[j] = (__bf16)in[j >> 2][j & 3];
@@ -114,7 +114,7 @@ struct Mlp<H, K, 1, E> {
   }
 
   // h = relu(W_0 x)
-  __device__ static void layer0(const __bf16* lds, const Input& x, float (&h)[MTH][4], int lane) {
+  __device__ __forceinline__ static void layer0(const __bf16* lds, const Input& x, float (&h)[MTH][4], int lane) {
     layer0_linear(lds, x, h, lane);
 #pragma unroll
     for (int mt = 0; mt < MTH; ++mt)
@@ -126,14 +126,14 @@ struct Mlp<H, K, 1, E> {
   // ReLU applied to the packed BF16 values (one 16-bit integer max per pair:
   // BF16 keeps the sign bit on top, and rounding never changes a sign, so
   // this equals rounding relu(y)).
-  __device__ static uint32_t relu_pair(float lo, float hi) {
+  __device__ __forceinline__ static uint32_t relu_pair(float lo, float hi) {
     typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
     typedef __attribute__((ext_vector_type(2))) float f32x2;
     typedef __attribute__((ext_vector_type(2))) short s16x2;
     const bf16x2 p = __builtin_convertvector((f32x2){lo, hi}, bf16x2);
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2)0));
   }
-  __device__ static void relu_operands(const float (&y)[MTH][4], bf16x8 (&b)[KBH]) {
+  __device__ __forceinline__ static void relu_operands(const float (&y)[MTH][4], bf16x8 (&b)[KBH]) {
     typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 #pragma unroll
     for (int kb = 0; kb < KBH; ++kb) {
@@ -144,7 +144,7 @@ struct Mlp<H, K, 1, E> {
   }
 
   // W_0 x without the ReLU
-  __device__ static void layer0_linear(const __bf16* lds, const Input& x, float (&y)[MTH][4], int lane) {
+  __device__ __forceinline__ static void layer0_linear(const __bf16* lds, const Input& x, float (&y)[MTH][4], int lane) {
 #pragma unroll
     for (int mt = 0; mt < MTH; ++mt) {
       f32x4 acc;
@@ -164,7 +164,7 @@ struct Mlp<H, K, 1, E> {
   // NB vertex blocks at once: each weight fragment read from LDS feeds NB
   // MFMAs, which divides the LDS traffic per FLOP by NB
   template <int NB>
-  __device__ static void layer0_linear_nb(const __bf16* lds, const Input (&x)[NB], float (&y)[NB][MTH][4],
+  __device__ __forceinline__ static void layer0_linear_nb(const __bf16* lds, const Input (&x)[NB], float (&y)[NB][MTH][4],
                                           int lane) {
 #pragma unroll
     for (int mt = 0; mt < MTH; ++mt) {
@@ -186,7 +186,7 @@ struct Mlp<H, K, 1, E> {
     }
   }
   template <int MT, int NB>
-  __device__ static void gemm_op_nb(const __bf16* lds, const bf16x8 (&b)[NB][KBH], float (&out)[NB][MT][4],
+  __device__ __forceinline__ static void gemm_op_nb(const __bf16* lds, const bf16x8 (&b)[NB][KBH], float (&out)[NB][MT][4],
                                     int lane) {
     const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
 #pragma unroll
@@ -209,7 +209,7 @@ struct Mlp<H, K, 1, E> {
 
   // out = W in over MT row tiles from ready B operands
   template <int MT>
-  __device__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
+  __device__ __forceinline__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
     const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -223,7 +223,7 @@ struct Mlp<H, K, 1, E> {
 
   // out = W in over MT row tiles, W fragments [MT][KBH][64] at `lds`
   template <int MT>
-  __device__ static void gemm(const __bf16* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
+  __device__ __forceinline__ static void gemm(const __bf16* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
     const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
     bf16x8 b[KBH];
 #pragma unroll
@@ -248,44 +248,75 @@ struct Mlp<H, K, 1, E> {
 // 16x16x4 f32 MFMA; weights row-major in LDS with an odd pitch.
 template <int H, int K, int E>
 struct Mlp<H, K, 0, E> {
-  static_assert(E == 0, "the encoded input is compiled for BF16 networks");
   static constexpr int MTH = H / 16;
   static constexpr int MTO = K / 2;
-  struct Input { float x[3]; };   // features kb*4 + g for kb = 0..2
+  static constexpr int IN = E ? kInEncoded : kInPadded;   // layer 0's packed input width
+  static constexpr int KB0 = E ? kInEncoded / 4 : 3;       // 4-wide contraction blocks of layer 0
+  // inputs kb*4 + g for kb < KB0
+  struct Input { float x[KB0]; };
 
-  __device__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
+  // raw: features, then the constant one, then zeros. Encoded (the same
+  // inputs as the BF16 network's): one-blob bin k % 19 of position
+  // coordinate k / 19 for k < 57, then omega_o, n and the constant one.
+  __device__ __forceinline__ static Input load_input(const float* __restrict__ feat, int64_t ld, int64_t v, bool valid, int g) {
     Input in;
-#pragma unroll
-    for (int kb = 0; kb < 3; ++kb) {
-      int k = kb * 4 + g;
-      float x = 0.0f;
+    if constexpr (E == 1) {
+      float p[3] = {0.0f, 0.0f, 0.0f};
+      float wo = 0.0f, nn = 0.0f;
       if (valid) {
-        if (k < kInFeatures) x = feat[(int64_t)k * ld + v];
-        else if (k == kInFeatures) x = 1.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p[i] = feat[(int64_t)i * ld + v];
+        if (g >= 1) wo = feat[(int64_t)(3 + g - 1) * ld + v];   // k = 56 + g: omega_o[g - 1]
+        if (g <= 2) nn = feat[(int64_t)(6 + g) * ld + v];       // k = 60 + g: n[g]
       }
-      in.x[kb] = x;
+      constexpr float kHalfLog2e = 0.72134752044448170368f;   // log2(e) / 2
+#pragma unroll
+      for (int kb = 0; kb < KB0; ++kb) {
+        const int k = kb * 4 + g;
+        float val;
+        if (kb == 14 && g >= 1) val = wo;
+        else if (kb == 15) val = g == 3 ? 1.0f : nn;
+        else {
+          const int d = (k >= 2 * kBlobBins) ? 2 : (k >= kBlobBins ? 1 : 0);
+          const float s = d == 0 ? p[0] : (d == 1 ? p[1] : p[2]);
+          const float t = fmaf(s, (float)kBlobBins, -((float)(k - kBlobBins * d) + 0.5f));
+          val = __builtin_amdgcn_exp2f(-kHalfLog2e * t * t);
+        }
+        in.x[kb] = valid ? val : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < KB0; ++kb) {
+        int k = kb * 4 + g;
+        float x = 0.0f;
+        if (valid) {
+          if (k < kInFeatures) x = feat[(int64_t)k * ld + v];
+          else if (k == kInFeatures) x = 1.0f;
+        }
+        in.x[kb] = x;
+      }
     }
     return in;
   }
 
-  // layer 0's input into rows 0..15 of a staging buffer: rows kb*4 + g hold
-  // this lane's x.x[kb], rows 12..15 are zero padding
+  // layer 0's input into rows 0..IN-1 of a staging buffer: rows kb*4 + g
+  // hold this lane's x.x[kb]; for the raw input rows 12..15 are zero padding
   template <typename S, int SP>
-  __device__ static void stage_input(S* st, const Input& x, int wave, int lane) {
+  __device__ __forceinline__ static void stage_input(S* st, const Input& x, int wave, int lane) {
     const int g = lane >> 4, c = lane & 15;
 #pragma unroll
-    for (int kb = 0; kb < 3; ++kb) st[(kb * 4 + g) * SP + wave * 16 + c] = (S)x.x[kb];
-    st[(12 + g) * SP + wave * 16 + c] = (S)0.0f;
+    for (int kb = 0; kb < KB0; ++kb) st[(kb * 4 + g) * SP + wave * 16 + c] = (S)x.x[kb];
+    if constexpr (E == 0) st[(12 + g) * SP + wave * 16 + c] = (S)0.0f;
   }
 
-  __device__ static void layer0(const float* lds, const Input& x, float (&h)[MTH][4], int lane) {
+  __device__ __forceinline__ static void layer0(const float* lds, const Input& x, float (&h)[MTH][4], int lane) {
     const int g = lane >> 4, c = lane & 15;
-    constexpr int P = kInPadded + 1;
+    constexpr int P = IN + 1;
 #pragma unroll
     for (int mt = 0; mt < MTH; ++mt) {
       f32x4 acc = zero4();
 #pragma unroll
-      for (int kb = 0; kb < 3; ++kb) acc = mfma_f32_4(lds[(mt * 16 + c) * P + kb * 4 + g], x.x[kb], acc);
+      for (int kb = 0; kb < KB0; ++kb) acc = mfma_f32_4(lds[(mt * 16 + c) * P + kb * 4 + g], x.x[kb], acc);
 #pragma unroll
       for (int i = 0; i < 4; ++i) h[mt][i] = relu(acc[i]);
     }
@@ -294,7 +325,7 @@ struct Mlp<H, K, 0, E> {
   // out = W in; W row-major [MT*16][H+1] at `lds`, input neuron of slot (kb, g)
   // is (kb/4)*16 + 4g + kb%4 = accumulator in[kb/4][kb%4] of this lane
   template <int MT>
-  __device__ static void gemm(const float* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
+  __device__ __forceinline__ static void gemm(const float* lds, const float (&in)[MTH][4], float (&out)[MT][4], int lane) {
     const int g = lane >> 4, c = lane & 15;
     constexpr int P = H + 1;
 #pragma unroll
@@ -319,7 +350,7 @@ struct Forward {
   static constexpr int MTO = M::MTO + S;   // output row tiles
 
   // offsets (elements) of each layer's forward weights in LDS
-  __device__ static const W* layer_ptr(const W* lds, int l, int nh) {
+  __device__ __forceinline__ static const W* layer_ptr(const W* lds, int l, int nh) {
     if (PREC == 1) {
       Bf16Layout Lt{NetDims{H, nh, K, S, E}};
       return lds + Lt.fwd_off(l);
@@ -332,7 +363,7 @@ struct Forward {
   // h[l] receives hidden layer l's activation for l < nh; `last` the one the
   // output layer reads (h[nh-1]). Layers past nh are skipped with uniform
   // branches; no array is indexed by a runtime value.
-  __device__ static void run(const W* lds, int nh, const typename M::Input& x,
+  __device__ __forceinline__ static void run(const W* lds, int nh, const typename M::Input& x,
                              float (&h)[NHMAX][M::MTH][4], float (&last)[M::MTH][4],
                              float (&out)[MTO][4], int lane) {
     M::layer0(layer_ptr(lds, 0, nh), x, h[0], lane);
@@ -359,7 +390,7 @@ struct Forward {
 
   // BF16 query forward of NB vertex blocks sharing every weight fragment read
   template <int NB>
-  __device__ static void run_query_nb(const W* lds, int nh, const typename M::Input (&x)[NB],
+  __device__ __forceinline__ static void run_query_nb(const W* lds, int nh, const typename M::Input (&x)[NB],
                                       float (&out)[NB][MTO][4], int lane) {
     static_assert(PREC == 1, "BF16 only");
     float y[NB][M::MTH][4];
@@ -380,7 +411,7 @@ struct Forward {
 
   // Forward for queries (no activations kept): in BF16 the layers pass
   // packed, ReLU'd B operands; the same values as run().
-  __device__ static void run_query(const W* lds, int nh, const typename M::Input& x, float (&out)[MTO][4],
+  __device__ __forceinline__ static void run_query(const W* lds, int nh, const typename M::Input& x, float (&out)[MTO][4],
                                    int lane) {
     if constexpr (PREC == 1) {
       float y[M::MTH][4];

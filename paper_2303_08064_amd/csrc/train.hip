@@ -49,11 +49,11 @@ struct TrainCfg {
 template <int H, int K, int PREC, int SEL>
 struct TrainLds {
   typedef typename std::conditional<PREC == 1, __bf16, float>::type W;
-  __device__ static const W* fwd(const W* lds, int l, int nh) {
+  __device__ __forceinline__ static const W* fwd(const W* lds, int l, int nh) {
     if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K, SEL}}.fwd_off(l);
     return lds + F32Layout{NetDims{H, nh, K, SEL}}.off(l);
   }
-  __device__ static const W* bwd(const W* lds, int l, int nh) {
+  __device__ __forceinline__ static const W* bwd(const W* lds, int l, int nh) {
     if (PREC == 1) return lds + Bf16Layout{NetDims{H, nh, K, SEL}}.bwd_off(l);
     return lds + F32Layout{NetDims{H, nh, K, SEL}}.off(l);
   }

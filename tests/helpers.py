@@ -21,9 +21,10 @@ CONFIGS = {
     "c1s_f32": (64, 3, 4, "f32"),
     # the paper's default network (Sec. 4.1, Sec. 6): encoded input, selection output
     "paper_bf16": (128, 4, 8, "bf16"),
+    "paper_f32": (128, 4, 8, "f32"),
 }
-SELECTION = {"c2s_f32", "c3s_bf16", "c1s_f32", "paper_bf16"}
-ENCODED = {"paper_bf16"}
+SELECTION = {"c2s_f32", "c3s_bf16", "c1s_f32", "paper_bf16", "paper_f32"}
+ENCODED = {"paper_bf16", "paper_f32"}
 
 
 def weights_for(name, seed=42, out_scale=1.0):

@@ -1,6 +1,9 @@
 """The paper's default network on the GPU against the FP64 oracle, through
 the C ABI: four hidden layers of 128 units, K = 8 lobes plus the selection
-output, and the encoded input of Tab. "encoding" (Sec. 4.1, Sec. 6), BF16.
+output, and the encoded input of Tab. "encoding" (Sec. 4.1, Sec. 6), BF16
+and FP32. The FP32 network is held to the FP32 bounds of the other
+networks: raw outputs 1e-5 per row, the loss 1e-5 relative, weight gradients
+1e-4 stage-wise and 1e-3 end to end.
 
 The kernels encode the 9 raw features on the device (one-blob bins of the
 position, omega_o, n, the constant one); the oracle encodes in float64 and
@@ -187,3 +190,41 @@ def test_paper_schedule_training_gain():
     assert kl > -0.02
     assert kl < 0.5 * kl_uniform
     assert c1 > c0 + 0.1
+
+
+@pytest.mark.parametrize("B", [1000, 64 * 50 + 17])
+def test_f32_forward_query_and_selection(B):
+    g, mats = make_guide("paper_f32", out_scale=2.0, mis_fraction=E, max_batch=1 << 16)
+    feat, _, _, _ = _batch(B, 70)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    ref = omlp.forward(w64(mats), feat.T).numpy()
+    err = np.linalg.norm(raw - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() < 1e-5, err.max()
+    xi = synth.uniforms(B, synth.rng_for(71))
+    sel = torch.empty(B, device="cuda")
+    d, pdf = g.query(to_dev(feat), to_dev(xi), sel_out=sel)
+    assert np.abs(sel.cpu().numpy() - onasg.selection(torch.tensor(ref), K).numpy()).max() < 1e-5
+    lob = onasg.decode(torch.tensor(raw), K)
+    lq = onasg.mixture_log_pdf(torch.tensor(d.cpu().numpy().T.astype(np.float64)), lob).numpy()
+    assert np.median(np.abs(np.log(pdf.cpu().numpy()) - lq)) < 1e-6
+
+
+@pytest.mark.parametrize("B", [777, 4096 + 35])
+def test_f32_blended_loss_grad(B):
+    g, mats = make_guide("paper_f32", out_scale=2.0, mis_fraction=E, max_batch=B)
+    feat, dirs, w, pdf = _batch(B, 72)
+    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+    torch.cuda.synchronize()
+    W = w64(mats)
+    w64v, pdf64 = w.astype(np.float64), pdf.astype(np.float64)
+    L, grads = otrain.blended_loss_and_grad(W, feat.T, dirs.T, w64v, pdf64, K, e=E)
+    assert abs(float(g.stats[0]) - L) <= 1e-5 * abs(L), (float(g.stats[0]), L)
+    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+    g_raw = otrain.blended_raw_output_grad(raw, dirs.T, w64v, pdf64, K, e=E)
+    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
+    gg = [t.numpy() for t in g.split(g.grad.cpu())]
+    errs = [_rel(a, b.numpy()) for a, b in zip(gg, staged)]
+    assert max(errs) < 1e-4, errs
+    assert _rel(gg[-1][-1], staged[-1][-1].numpy()) < 1e-4
+    errs_e2e = [_rel(a, b.numpy()) for a, b in zip(gg, grads)]
+    assert max(errs_e2e) < 1e-3, errs_e2e

@@ -121,9 +121,12 @@ def test_encoded_network_sizes(lib):
     H = 128
     assert lib.nasg_packed_bytes(ctypes.byref(c)) == 2 * (64 * H + 3 * H * H + 80 * H + 3 * H * H + 64 * H + 16 * H)
     assert lib.nasg_workspace_bytes(ctypes.byref(c)) >= 256 * nw * 4 + 4096 * 80 * 2
+    # FP32: row-major layers with odd pitches (65 for layer 0, 129 after), 80 output rows
+    c32 = _cfg(hidden=128, n_lobes=8, selection=1, encoding=1, precision=0, max_batch=4096)
+    assert lib.nasg_packed_bytes(ctypes.byref(c32)) == 4 * (128 * 65 + 3 * 128 * 129 + 80 * 129)
+    assert lib.nasg_workspace_bytes(ctypes.byref(c32)) >= 256 * nw * 4 + 4096 * 80 * 4
     # only that combination carries the encoded input
     for kw in (dict(hidden=64, n_lobes=8, selection=1, encoding=1),
-               dict(hidden=128, n_lobes=8, selection=1, encoding=1, precision=0),
                dict(hidden=128, n_lobes=8, selection=0, encoding=1),
                dict(hidden=128, n_lobes=32, selection=0, encoding=1),
                dict(hidden=128, n_lobes=8, selection=1, encoding=0),
