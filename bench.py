@@ -110,13 +110,13 @@ class PaperFrame:
     """One frame of the paper's default configuration: the same four bounces
     of queries, then T Adam steps of t samples each on the blended loss."""
 
-    def __init__(self, seed=3000):
+    def __init__(self, seed=3000, precision="bf16"):
         import torch
         from paper_2303_08064_amd import synth
         from paper_2303_08064_amd.nasg import NasgGuide
         self.torch = torch
         mats = synth.init_weights(synth.layer_shapes(128, 4, 8, selection=True, encoded=True), synth.rng_for(42))
-        self.guide = NasgGuide(synth.flat_weights(mats), hidden=128, n_hidden=4, n_lobes=8, precision="bf16",
+        self.guide = NasgGuide(synth.flat_weights(mats), hidden=128, n_hidden=4, n_lobes=8, precision=precision,
                                lr=1e-3, max_batch=PAPER_TB, selection=True, mis_fraction=0.2, encoded=True)
         rng = synth.rng_for(seed)
         dev = "cuda"
@@ -140,9 +140,10 @@ class PaperFrame:
             g.train_step(f, d, w, bsdf_pdf=pdf)
 
 
-def paper_leg(steps, use_graph):
+def paper_leg(steps, use_graph, fp32=True):
     """The paper's default configuration, timed like the main frame, plus
-    its query and single training step on their own."""
+    its query and single training step on their own, and the same frame
+    with the FP32 network."""
     fr = PaperFrame()
     ms, _ = time_frames(fr, steps, 2, use_graph)
     g = fr.guide
@@ -153,6 +154,13 @@ def paper_leg(steps, use_graph):
     nq = sum(BOUNCES)
     ns = PAPER_T * PAPER_TB
     q_fl = mlp_flops_net(128, 4, 8, 64, 1)
+    extra = {}
+    if fp32:
+        del fr
+        f32 = PaperFrame(precision="f32")
+        ms32, _ = time_frames(f32, max(3, steps // 4), 1, use_graph)
+        extra = {"fp32_ms_per_frame": round(ms32, 4), "speedup_bf16": round(ms32 / ms, 3)}
+        del f32
     return {
         "workload": "paper default: encoded input (one-blob 57 + omega_o + n + 1 = 64) -> 128x4 -> 8*8+1 "
                     "(K=8 with selection), BF16; queries 2^20+600000+300000+120000 and 16 Adam steps of "
@@ -161,6 +169,7 @@ def paper_leg(steps, use_graph):
         "train_samples_per_s": round(ns / (ms * 1e-3), 1),
         "query_2e20_ms": round(ms_q, 4), "query_mfma_tflops": round(q_fl * (1 << 20) / (ms_q * 1e-3) / 1e12, 1),
         "train_step_4096_us": round(ms_t * 1e3, 1),
+        **extra,
     }
 
 
