@@ -7,20 +7,23 @@
 
 namespace nasg {
 
+// The record is read exactly once, so its loads are non-temporal (they do
+// not displace other data in the caches).
 template <int K>
 __device__ __forceinline__ void load_records(const float* __restrict__ rec, int64_t v, Lobe (&lb)[K]) {
   const float* base = rec + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+  auto ld = [&](int p, int k) { return __builtin_nontemporal_load(base + (p * K + k) * kRecTile); };
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    lb[k].zx = base[(0 * K + k) * kRecTile];
-    lb[k].zy = base[(1 * K + k) * kRecTile];
-    lb[k].zz = base[(2 * K + k) * kRecTile];
-    lb[k].xx = base[(3 * K + k) * kRecTile];
-    lb[k].xy = base[(4 * K + k) * kRecTile];
-    lb[k].xz = base[(5 * K + k) * kRecTile];
-    lb[k].lam = base[(6 * K + k) * kRecTile];
-    lb[k].a = base[(7 * K + k) * kRecTile];
-    lb[k].logc = base[(8 * K + k) * kRecTile];
+    lb[k].zx = ld(0, k);
+    lb[k].zy = ld(1, k);
+    lb[k].zz = ld(2, k);
+    lb[k].xx = ld(3, k);
+    lb[k].xy = ld(4, k);
+    lb[k].xz = ld(5, k);
+    lb[k].lam = ld(6, k);
+    lb[k].a = ld(7, k);
+    lb[k].logc = ld(8, k);
   }
 }
 
