@@ -228,3 +228,30 @@ def test_f32_blended_loss_grad(B):
     assert _rel(gg[-1][-1], staged[-1][-1].numpy()) < 1e-4
     errs_e2e = [_rel(a, b.numpy()) for a, b in zip(gg, grads)]
     assert max(errs_e2e) < 1e-3, errs_e2e
+
+
+@pytest.mark.parametrize("name", [NAME, "paper_f32"])
+def test_edge_batches(name):
+    """B = 0 launches nothing; B = 1 and B = 17 (one partial tile) match the
+    oracle; B above max_batch is refused."""
+    from paper_2303_08064_amd._lib import NasgError
+    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E, max_batch=64)
+    z9, z4 = torch.zeros(9, 0, device="cuda"), torch.zeros(4, 0, device="cuda")
+    d, p = g.query(z9, z4)
+    assert d.shape == (3, 0) and p.shape == (0,)
+    assert g.forward_raw(z9).shape == (8 * K + 1, 0)
+    W = w64(mats)
+    bf16 = name == NAME
+    for B in (1, 17):
+        feat, dirs, w, pdf = _batch(B, 80 + B)
+        raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
+        ref = omlp.forward(W, feat.T, bf16=bf16).numpy()
+        assert (np.abs(raw - ref) / np.abs(ref).max(axis=1, keepdims=True)).max() < (2e-2 if bf16 else 1e-5)
+        g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
+        torch.cuda.synchronize()
+        L = float(otrain.blended_nll(W, feat.T, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E,
+                                     bf16=bf16))
+        assert abs(float(g.stats[0]) - L) <= (1e-3 if bf16 else 1e-5) * abs(L), (B, float(g.stats[0]), L)
+    feat, dirs, w, pdf = _batch(65, 90)
+    with pytest.raises(NasgError, match="max_batch"):
+        g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
