@@ -282,6 +282,33 @@ def test_sampler_chi_square_against_pdf(lam, a, eps):
     assert ss.chi2.sf(chi2, dof) > 1e-4
 
 
+@pytest.mark.parametrize("lam,a,eps", [(1.0, 0.0, 0.0), (10.0, 10.0, 0.0), (25.0, 100.0, 0.0),
+                                       (3.0, 5.0, 0.3), (0.2, 30.0, 0.0), (200.0, 4.0, 0.0)])
+def test_sampler_density_by_jacobian(lam, a, eps):
+    """App. C pointwise: the map (xi0, xi1) -> v of one hemisphere carries
+    probability 1/2 with uniform density, so the solid-angle density at v is
+    1 / (2 |dv/dxi0 x dv/dxi1|). By central differences of the sampler this
+    equals G(v)/K with K in closed form (App. B), at every sample."""
+    rng = np.random.default_rng(7)
+    z, x, y = random_frame(rng)
+    n, h = 400, 1e-6
+    xi = 0.05 + 0.9 * rng.random((n, 3))
+    T = lambda t: torch.tensor(t, dtype=F64)
+
+    def smp(x0, x1):
+        return nasg.sample_lobe(T(z).expand(n, 3), T(x).expand(n, 3), T(y).expand(n, 3),
+                                T(np.full(n, lam)), T(np.full(n, a)),
+                                T(x0), T(x1), T(xi[:, 2]), eps).numpy()
+
+    v = smp(xi[:, 0], xi[:, 1])
+    d0 = (smp(xi[:, 0] + h, xi[:, 1]) - smp(xi[:, 0] - h, xi[:, 1])) / (2 * h)
+    d1 = (smp(xi[:, 0], xi[:, 1] + h) - smp(xi[:, 0], xi[:, 1] - h)) / (2 * h)
+    dens = 0.5 / np.linalg.norm(np.cross(d0, d1), axis=1)
+    lg = nasg.lobe_log_g(T(v), T(z), T(x), T(lam), T(a), eps).numpy()
+    logk = float(nasg.log_normaliser(T(lam), T(a), eps))
+    assert np.max(np.abs(dens / np.exp(lg - logk) - 1)) < 1e-5
+
+
 def test_sample_value_matches_sampling_variables():
     """At a sampled direction, G equals s * u^{p-1} with u = (cos theta + 1)/2
     and p = 1 + eps + a cos^2 phi, from Phi^{-1} (App. C)."""
