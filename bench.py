@@ -144,11 +144,16 @@ def paper_leg(steps, use_graph, fp32=True):
     """The paper's default configuration, timed like the main frame, plus
     its query and single training step on their own, and the same frame
     with the FP32 network."""
+    import torch
     fr = PaperFrame()
     ms, _ = time_frames(fr, steps, 2, use_graph)
     g = fr.guide
     (f, xi), (d, p, c) = fr.q_in[0], fr.q_out[0]
     ms_q = kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p, sel_out=c), 10)
+    # the MLP alone: the raw forward of the same 2^20 vertices (no NASG work)
+    raw = torch.empty(g.n_out, f.shape[1], dtype=torch.float32, device=f.device)
+    ms_f = kernel_avg_ms(lambda: g.forward_raw(f, out=raw), 10)
+    del raw
     f0, d0, w0, p0 = fr.t_in[0]
     ms_t = kernel_avg_ms(lambda: g.train_step(f0, d0, w0, bsdf_pdf=p0), 20)
     nq = sum(BOUNCES)
@@ -168,6 +173,8 @@ def paper_leg(steps, use_graph, fp32=True):
         "ms_per_frame": round(ms, 4), "queries_per_s": round(nq / (ms * 1e-3), 1),
         "train_samples_per_s": round(ns / (ms * 1e-3), 1),
         "query_2e20_ms": round(ms_q, 4), "query_mfma_tflops": round(q_fl * (1 << 20) / (ms_q * 1e-3) / 1e12, 1),
+        "forward_2e20_ms": round(ms_f, 4),
+        "forward_mfma_frac_bf16": round(q_fl * (1 << 20) / (ms_f * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4),
         "train_step_4096_us": round(ms_t * 1e3, 1),
         **extra,
     }
@@ -467,10 +474,9 @@ def main():
         g = NasgGuide(synth.flat_weights(mats), hidden=128, n_hidden=4, n_lobes=32, precision="bf16", max_batch=n)
         f, d, w = synth.training_batch(n, synth.rng_for(1004), synth.AnisoTarget(8, seed=1005))
         b = (torch.from_numpy(f).cuda(), torch.from_numpy(d).cuda(), torch.from_numpy(w).cuda())
-        for _ in range(a.steps):
-            g.train_step(*b)
-        torch.cuda.synchronize()
-        print(json.dumps({"only": "c5", "steps": a.steps}))
+        g.train_step(*b)
+        ms = kernel_avg_ms(lambda: g.train_step(*b), a.steps)
+        print(json.dumps({"only": "c5", "steps": a.steps, "ms_per_step": round(ms, 4)}))
         return
     if a.only in ("paper_query", "paper_train"):
         fr = PaperFrame()
@@ -484,7 +490,7 @@ def main():
         print(json.dumps({"only": a.only, "steps": a.steps}))
         return
     if a.only == "paper":
-        print(json.dumps({"only": "paper", **paper_leg(a.steps, not a.no_graph)}))
+        print(json.dumps({"only": "paper", **paper_leg(a.steps, not a.no_graph, fp32=not a.no_fp32)}))
         return
     if a.only == "records":
         print(json.dumps({"only": "records", **records_legs(frame, a.steps)}))

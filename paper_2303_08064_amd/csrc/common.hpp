@@ -53,6 +53,33 @@ __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__flo
 
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.0f, 0.0f, 0.0f, 0.0f}; }
 
+// acc[nb][mt] = sum over kb of A[mt][kb] b[nb][kb] for MT row tiles and KB
+// 32-wide contraction blocks, the A fragments [MT][KB][64 lanes] at `frag`
+// (LDS). The steps run block-major (kb outer, row tiles inner), so
+// consecutive MFMAs accumulate into different tiles instead of waiting on
+// each other, and the fragment of step s + PF is requested before step s is
+// multiplied, so PF LDS reads are in flight behind the MFMAs.
+// bop(nb, kb) returns the B operand b[nb][kb].
+template <int MT, int KB, int NB, int PF = 4, typename BOp>
+__device__ __forceinline__ void mfma_rows(const bf16x8* frag, BOp bop, f32x4 (&acc)[NB][MT], int lane) {
+  constexpr int N = MT * KB;
+  constexpr int D = PF < N ? PF : N;
+  bf16x8 a[D + 1];
+#pragma unroll
+  for (int s = 0; s < D; ++s) a[s] = frag[((s % MT) * KB + s / MT) * 64 + lane];
+#pragma unroll
+  for (int s = 0; s < N; ++s) {
+    if (s + D < N) {
+      const int t = s + D;
+      a[t % (D + 1)] = frag[((t % MT) * KB + t / MT) * 64 + lane];
+    }
+    const int kb = s / MT, mt = s % MT;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      acc[nb][mt] = mfma_bf16_32(a[s % (D + 1)], bop(nb, kb), kb == 0 ? zero4() : acc[nb][mt]);
+  }
+}
+
 // Copy `bytes` (multiple of 16) from global to LDS with the whole block.
 __device__ __forceinline__ void block_copy_to_lds(void* lds, const void* src, int bytes) {
   const uint4* s = reinterpret_cast<const uint4*>(src);

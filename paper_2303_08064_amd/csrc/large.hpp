@@ -439,7 +439,8 @@ __device__ __forceinline__ void stage_act(S* st, const Act<PREC, MTH>& h, int wa
 // operands (K/4 16-byte slots per lane, then with the selection output one
 // 8-byte slot of the selection tile's 16x16x16 operand); FP32 as the
 // accumulator image (K/2 16-byte slots per lane, one more for the selection
-// tile).
+// tile). Written once and read once, by non-temporal stores and loads, so
+// the stream does not displace the weights in L2.
 template <int K, int PREC, int SEL = 0>
 struct DOut {
   static constexpr int MTO = K / 2 + SEL, KBO = K / 4;     // FP32: every output tile
@@ -447,14 +448,16 @@ struct DOut {
   __device__ __forceinline__ static void store(void* base, int64_t tile16, const float (&dl)[MTO][4], int lane) {
     float4* d = reinterpret_cast<float4*>(base) + tile16 * MTO * 64 + lane;
 #pragma unroll
-    for (int mt = 0; mt < MTO; ++mt) d[mt * 64] = float4{dl[mt][0], dl[mt][1], dl[mt][2], dl[mt][3]};
+    for (int mt = 0; mt < MTO; ++mt)
+      __builtin_nontemporal_store(f32x4{dl[mt][0], dl[mt][1], dl[mt][2], dl[mt][3]},
+                                  reinterpret_cast<f32x4*>(d + mt * 64));
   }
   __device__ __forceinline__ static void load(const void* base, int64_t tile16, float (&dl)[MTO][4], int lane) {
     const float4* s = reinterpret_cast<const float4*>(base) + tile16 * MTO * 64 + lane;
 #pragma unroll
     for (int mt = 0; mt < MTO; ++mt) {
-      const float4 x = s[mt * 64];
-      dl[mt][0] = x.x; dl[mt][1] = x.y; dl[mt][2] = x.z; dl[mt][3] = x.w;
+      const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(s + mt * 64));
+      dl[mt][0] = x[0]; dl[mt][1] = x[1]; dl[mt][2] = x[2]; dl[mt][3] = x[3];
     }
   }
   // BF16: the stored slots are exactly the output layer's dgrad B operands
@@ -463,15 +466,15 @@ struct DOut {
     __bf16* blk = reinterpret_cast<__bf16*>(base) + tile16 * BLOCK;
     bf16x8* d = reinterpret_cast<bf16x8*>(blk) + lane;
 #pragma unroll
-    for (int kb = 0; kb < KBO; ++kb) d[kb * 64] = b[kb];
-    if constexpr (SEL == 1) reinterpret_cast<bf16x4*>(blk + KBO * 512)[lane] = bs;
+    for (int kb = 0; kb < KBO; ++kb) __builtin_nontemporal_store(b[kb], d + kb * 64);
+    if constexpr (SEL == 1) __builtin_nontemporal_store(bs, reinterpret_cast<bf16x4*>(blk + KBO * 512) + lane);
   }
   __device__ __forceinline__ static void load_operands(const void* base, int64_t tile16, bf16x8 (&b)[KBO], bf16x4& bs, int lane) {
     const __bf16* blk = reinterpret_cast<const __bf16*>(base) + tile16 * BLOCK;
     const bf16x8* s = reinterpret_cast<const bf16x8*>(blk) + lane;
 #pragma unroll
-    for (int kb = 0; kb < KBO; ++kb) b[kb] = s[kb * 64];
-    if constexpr (SEL == 1) bs = reinterpret_cast<const bf16x4*>(blk + KBO * 512)[lane];
+    for (int kb = 0; kb < KBO; ++kb) b[kb] = __builtin_nontemporal_load(s + kb * 64);
+    if constexpr (SEL == 1) bs = __builtin_nontemporal_load(reinterpret_cast<const bf16x4*>(blk + KBO * 512) + lane);
   }
 };
 
@@ -736,7 +739,9 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[MTO - 1][j];
       }
-      if constexpr (GROUP == 1) DO::store_operands(a.dout, blk, bo, bs, lane);
+      // stored for the separate group-0 kernel only (in the one-launch
+      // schedule group 0 evaluates its own)
+      if constexpr (GROUP == 1 && !SINGLE) DO::store_operands(a.dout, blk, bo, bs, lane);
       if constexpr (RES) N::sync_stage();                                       // output-dgrad stage 0 in b0
     } else {
       N::hidden(wg, b0, b1, x, hp, out_bwd, N::OB_STAGE, lane);   // leaves output-dgrad stage 0 in b0

@@ -185,29 +185,48 @@ struct Mlp<H, K, 1, E> {
         for (int i = 0; i < 4; ++i) y[nb][mt][i] = acc[nb][i];
     }
   }
-  template <int MT, int NB>
+  // out[nb] = W b[nb] over MT row tiles for NB vertex blocks: each A
+  // fragment read from LDS feeds NB MFMAs. BM: block-major order with the
+  // fragments prefetched (mfma_rows), else row tile by row tile (fewer live
+  // registers). Measured on the hidden-128 query: block-major is faster
+  // ahead of the NASG epilogue, row-major for the raw forward alone.
+  template <int MT, int NB, bool BM>
   __device__ __forceinline__ static void gemm_op_nb(const __bf16* lds, const bf16x8 (&b)[NB][KBH], float (&out)[NB][MT][4],
                                     int lane) {
-    const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      f32x4 acc[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = zero4();
-#pragma unroll
-      for (int kb = 0; kb < KBH; ++kb) {
-        const bf16x8 a = frag[(mt * KBH + kb) * 64 + lane];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_bf16_32(a, b[nb][kb], acc[nb]);
-      }
+    if constexpr (BM) {
+      f32x4 acc[NB][MT];
+      mfma_rows<MT, KBH, NB>(reinterpret_cast<const bf16x8*>(lds), [&](int nb, int kb) { return b[nb][kb]; }, acc,
+                             lane);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[nb][mt][i] = acc[nb][i];
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) out[nb][mt][i] = acc[nb][mt][i];
+    } else {
+      const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x4 acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = zero4();
+#pragma unroll
+        for (int kb = 0; kb < KBH; ++kb) {
+          const bf16x8 a = frag[(mt * KBH + kb) * 64 + lane];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma_bf16_32(a, b[nb][kb], acc[nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) out[nb][mt][i] = acc[nb][i];
+      }
     }
   }
 
-  // out = W in over MT row tiles from ready B operands
+  // out = W in over MT row tiles from ready B operands (row tile by row
+  // tile: with one vertex block the block-major order of mfma_rows measured
+  // slower, its extra fragment registers spilling in the large kernels)
   template <int MT>
   __device__ __forceinline__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
     const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
@@ -389,7 +408,7 @@ struct Forward {
   }
 
   // BF16 query forward of NB vertex blocks sharing every weight fragment read
-  template <int NB>
+  template <int NB, bool BM>
   __device__ __forceinline__ static void run_query_nb(const W* lds, int nh, const typename M::Input (&x)[NB],
                                       float (&out)[NB][MTO][4], int lane) {
     static_assert(PREC == 1, "BF16 only");
@@ -401,12 +420,12 @@ struct Forward {
 #pragma unroll
     for (int l = 1; l < NHMAX; ++l) {
       if (l < nh) {
-        M::template gemm_op_nb<M::MTH, NB>(layer_ptr(lds, l, nh), b, y, lane);
+        M::template gemm_op_nb<M::MTH, NB, BM>(layer_ptr(lds, l, nh), b, y, lane);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) M::relu_operands(y[nb], b[nb]);
       }
     }
-    M::template gemm_op_nb<MTO, NB>(layer_ptr(lds, nh, nh), b, out, lane);
+    M::template gemm_op_nb<MTO, NB, BM>(layer_ptr(lds, nh, nh), b, out, lane);
   }
 
   // Forward for queries (no activations kept): in BF16 the layers pass

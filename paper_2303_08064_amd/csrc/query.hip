@@ -109,7 +109,7 @@ void query_kernel(QueryArgs a) {
         x[nb] = M::load_input(a.feat, a.ld, v, v < a.B, g);
       }
       float out[NB][F::MTO][4];
-      F::template run_query_nb<NB>(wts, a.nh, x, out, lane);
+      F::template run_query_nb<NB, MODE == 0>(wts, a.nh, x, out, lane);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) finish_block<K, MODE, S>(a, out[nb], tile * TV + nb * kTileV + c, g, c);
     }
