@@ -97,18 +97,28 @@ struct Pk {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // dp[MT0 .. MT0+NMT) of W^T dl from backward fragments [NMT][KB][64] at buf;
-// b holds dl as B operands.
-template <int KB, int NMT, int MT0, int MTP>
+// b holds dl as B operands. BM: block-major with prefetched fragments
+// (mfma_rows), else row tile by row tile.
+template <int KB, int NMT, int MT0, bool BM, int MTP>
 __device__ __forceinline__ void dgrad_rows(const __bf16* buf, const bf16x8 (&b)[KB], float (&dp)[MTP][4],
                                            int lane) {
-  const bf16x8* frag = reinterpret_cast<const bf16x8*>(buf);
+  if constexpr (BM) {
+    f32x4 acc[1][NMT];
+    mfma_rows<NMT, KB, 1>(reinterpret_cast<const bf16x8*>(buf), [&](int, int kb) { return b[kb]; }, acc, lane);
 #pragma unroll
-  for (int mt = 0; mt < NMT; ++mt) {
-    f32x4 acc = zero4();
+    for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+      for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[0][mt][i];
+  } else {
+    const bf16x8* frag = reinterpret_cast<const bf16x8*>(buf);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[i];
+    for (int mt = 0; mt < NMT; ++mt) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dp[MT0 + mt][i] = acc[i];
+    }
   }
 }
 
@@ -134,10 +144,12 @@ __device__ __forceinline__ void dgrad_sel(const __bf16* buf, const bf16x4& bs, f
 // reference and swap them where a layer ends on the other parity, so that
 // "resident in b0" always names the buffer the next stage computes from.
 // SEL = 1: one more output tile, the selection logit (row 8K); ENC = 1:
-// layer 0 reads the encoded input.
-template <int H, int K, int SEL = 0, int ENC = 0>
+// layer 0 reads the encoded input; BM_: the layers' MFMAs in block-major
+// order with prefetched fragments (for kernels with registers to spare).
+template <int H, int K, int SEL = 0, int ENC = 0, bool BM_ = false>
 struct NetBf16 {
   typedef Mlp<H, K, 1, ENC> M;
+  static constexpr bool BM = BM_;
   typedef __bf16 W;
   static constexpr int NH = 4;
   static constexpr int MTH = H / 16, MTO = K / 2 + SEL, KQ = K / 4;
@@ -191,7 +203,7 @@ struct NetBf16 {
       W* oth = (l & 1) ? b0 : b1;
       if (l + 1 < NH) dma(oth, wg + Lt.fwd_off(l + 1), H * H);
       else dma(oth, next, next_elems);
-      M::template gemm_op<MTH>(cur, b, y, lane);
+      M::template gemm_op<MTH, BM>(cur, b, y, lane);
       M::relu_operands(y, b);
       hp[l].from_ops(b);
       sync_stage();
@@ -209,7 +221,7 @@ struct NetBf16 {
       dma(b1, wg + Lt.fwd_off(NH) + OUT_STAGE, OUT_STAGE);
       {
         float part[HALF_O][4];
-        M::template gemm_op<HALF_O>(b0, b, part, lane);
+        M::template gemm_op<HALF_O, BM>(b0, b, part, lane);
 #pragma unroll
         for (int mt = 0; mt < HALF_O; ++mt)
 #pragma unroll
@@ -219,7 +231,7 @@ struct NetBf16 {
       dma(b0, next, next_elems);
       {
         float part[HALF_O][4];
-        M::template gemm_op<HALF_O>(b1, b, part, lane);
+        M::template gemm_op<HALF_O, BM>(b1, b, part, lane);
 #pragma unroll
         for (int mt = 0; mt < HALF_O; ++mt)
 #pragma unroll
@@ -228,7 +240,7 @@ struct NetBf16 {
       sync_stage();
     } else {
       dma(b1, next, next_elems);
-      M::template gemm_op<MTO>(b0, b, out, lane);
+      M::template gemm_op<MTO, BM>(b0, b, out, lane);
       sync_stage();
       swap(b0, b1);
     }
@@ -257,11 +269,11 @@ struct NetBf16 {
     hp[0].from_ops(b);
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
-      M::template gemm_op<MTH>(base + Lt.fwd_off(l), b, y, lane);
+      M::template gemm_op<MTH, BM>(base + Lt.fwd_off(l), b, y, lane);
       M::relu_operands(y, b);
       hp[l].from_ops(b);
     }
-    M::template gemm_op<MTO>(base + Lt.fwd_off(NH), b, out, lane);
+    M::template gemm_op<MTO, BM>(base + Lt.fwd_off(NH), b, out, lane);
   }
 
   // dh = W_out^T dl with the output layer's first backward stage resident in
@@ -271,14 +283,14 @@ struct NetBf16 {
                                    float (&dh)[MTH][4], const W* next, int next_elems, int lane) {
     if constexpr (NOUT == 2) {
       dma(b1, out_bwd + OB_STAGE, OB_STAGE);
-      dgrad_rows<KBO, MTH / 2, 0>(b0, bo, dh, lane);
+      dgrad_rows<KBO, MTH / 2, 0, BM>(b0, bo, dh, lane);
       sync_stage();
       dma(b0, next, next_elems);
-      dgrad_rows<KBO, MTH / 2, MTH / 2>(b1, bo, dh, lane);
+      dgrad_rows<KBO, MTH / 2, MTH / 2, BM>(b1, bo, dh, lane);
       sync_stage();
     } else {
       dma(b1, next, next_elems);
-      dgrad_rows<KBO, MTH, 0>(b0, bo, dh, lane);
+      dgrad_rows<KBO, MTH, 0, BM>(b0, bo, dh, lane);
       if constexpr (SEL == 1) dgrad_sel(b0 + 8 * K * H, bs, dh, lane);
       sync_stage();
       swap(b0, b1);
@@ -643,7 +655,10 @@ struct LargeLds {
 // use), so the forward waits for memory once instead of once per layer.
 template <int H, int K, int SEL, int ENC, int GROUP, bool OWN, bool SINGLE = false, bool RES = false>
 __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, int n_wg) {
-  typedef NetBf16<H, K, SEL, ENC> N;
+  // block-major MFMA order where the registers allow it: everywhere but the
+  // multi-tile group-1 kernel, whose gradient accumulators stay live across
+  // the forward and the epilogue
+  typedef NetBf16<H, K, SEL, ENC, GROUP == 0 || SINGLE> N;
   static_assert(!RES || (SINGLE && (GROUP == 1 || OWN)), "the resident forward: one tile, loss gradient here");
   typedef typename N::M M;
   typedef __bf16 W;
@@ -757,11 +772,11 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
       if constexpr (N::NOUT == 2) {
         dlw.template stage<SP, 0, MTH>(dst, wave, lane);           // output rows [0, 8K/2)
         N::dma(b1, out_bwd + N::OB_STAGE, N::OB_STAGE);
-        dgrad_rows<KBO, HALF_H, 0>(b0, bo, dh, lane);
+        dgrad_rows<KBO, HALF_H, 0, N::BM>(b0, bo, dh, lane);
         N::sync_stage();                                            // also publishes the staging
         wgrad_tiles<1, St, SP, 1, CTH, kBwdV>(dst, hst, rt, 1, accO[0], lane);
         N::dma(b0, wg + Lt.fwd_off(0), N::L0);                      // the next tile's layer 0
-        dgrad_rows<KBO, HALF_H, HALF_H>(b1, bo, dh, lane);
+        dgrad_rows<KBO, HALF_H, HALF_H, N::BM>(b1, bo, dh, lane);
         dhw.masked(dh, hp[NH - 1]);
         N::sync_stage();                                            // the first half has been read
         dlw.template stage<SP, MTH, MTH>(dst, wave, lane);          // output rows [8K/2, 8K)
@@ -770,7 +785,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
       } else {
         dlw.template stage<SP, 0, MTO>(dst, wave, lane);            // every output row
         if constexpr (!RES) N::dma(b1, wg + Lt.fwd_off(0), N::L0);  // the next tile's layer 0
-        dgrad_rows<KBO, MTH, 0>(b0, bo, dh, lane);
+        dgrad_rows<KBO, MTH, 0, N::BM>(b0, bo, dh, lane);
         if constexpr (SEL == 1) dgrad_sel(b0 + 8 * K * H, bs, dh, lane);
         N::sync_stage();                                            // also publishes the staging
         N::swap(b0, b1);
@@ -793,7 +808,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         dhw.ops(op);
         float d2[MTH][4];
         N::dma(b1, wg + Lt.bwd_off(NH - 2), H * H);
-        dgrad_rows<KBH, MTH, 0>(b0, op, d2, lane);                // through hidden layer NH-1
+        dgrad_rows<KBH, MTH, 0, N::BM>(b0, op, d2, lane);                // through hidden layer NH-1
         d2w.masked(d2, hp[NH - 2]);
         N::sync_stage();
       }
@@ -808,7 +823,7 @@ __device__ __forceinline__ void bwd_bf16_body(const LargeTrainArgs& a, int wgi, 
         bf16x8 op[KBH];
         d2w.ops(op);
         float dn[MTH][4];
-        dgrad_rows<KBH, MTH, 0>(cur, op, dn, lane);
+        dgrad_rows<KBH, MTH, 0, N::BM>(cur, op, dn, lane);
         Pk<MTH> dnw;
         dnw.masked(dn, hp[l - 1]);
         N::sync_stage();                                          // also publishes the staging

@@ -224,19 +224,29 @@ struct Mlp<H, K, 1, E> {
     }
   }
 
-  // out = W in over MT row tiles from ready B operands (row tile by row
-  // tile: with one vertex block the block-major order of mfma_rows measured
-  // slower, its extra fragment registers spilling in the large kernels)
-  template <int MT>
+  // out = W in over MT row tiles from ready B operands. BM: block-major
+  // with prefetched fragments (mfma_rows), else row tile by row tile, which
+  // keeps fewer registers live (block-major raised the spills of the
+  // multi-tile hidden-128 group-1 kernel and measured slower there).
+  template <int MT, bool BM = false>
   __device__ __forceinline__ static void gemm_op(const __bf16* lds, const bf16x8 (&b)[KBH], float (&out)[MT][4], int lane) {
-    const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
+    if constexpr (BM) {
+      f32x4 acc[1][MT];
+      mfma_rows<MT, KBH, 1>(reinterpret_cast<const bf16x8*>(lds), [&](int, int kb) { return b[kb]; }, acc, lane);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      f32x4 acc = zero4();
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int kb = 0; kb < KBH; ++kb) acc = mfma_bf16_32(frag[(mt * KBH + kb) * 64 + lane], b[kb], acc);
+        for (int i = 0; i < 4; ++i) out[mt][i] = acc[0][mt][i];
+    } else {
+      const bf16x8* frag = reinterpret_cast<const bf16x8*>(lds);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[mt][i] = acc[i];
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x4 acc = zero4();
+#pragma unroll
+        for (int kb = 0; kb < KBH; ++kb) acc = mfma_bf16_32(frag[(mt * KBH + kb) * 64 + lane], b[kb], acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[mt][i] = acc[i];
+      }
     }
   }
 
