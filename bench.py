@@ -443,8 +443,8 @@ def cpu_baseline(min_seconds=10.0, max_pieces=64, fraction=8):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the guiding hot path is data-parallel over vertices and "
-              "this build measures one GPU's share (see DESIGN.md for how it shards).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the guiding hot path is data-parallel over vertices, "
+              "and the figure reported is one GPU's throughput on its share of a frame.", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
