@@ -314,6 +314,17 @@ def train_leg(frame, reps=10):
     return {"avg_ms": round(ms, 4), "samples_per_s": round(TRAIN_B / (ms * 1e-3), 1)}
 
 
+def stage_legs(frame, reps=10):
+    """Microseconds per stage of one frame, each stage launched on its own:
+    the query of every bounce, then the training step."""
+    g = frame.guide
+    out = {}
+    for (f, xi), (d, p), n in zip(frame.q_in, frame.q_out, BOUNCES):
+        out[f"query_{n}"] = round(kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p), reps) * 1e3, 1)
+    out[f"train_step_{TRAIN_B}"] = round(kernel_avg_ms(lambda: g.train_step(*frame.t_in), reps) * 1e3, 1)
+    return out
+
+
 PEAK_F32_MFMA_TFLOPS = 157.3
 
 
@@ -432,12 +443,26 @@ def cpu_baseline(min_seconds=10.0, max_pieces=64, fraction=8):
         dt += time.perf_counter() - t0
         pieces += 1
     frames_per_s = (pieces / fraction) / dt
-    return {"value": round(frames_per_s * sum(BOUNCES), 1), "unit": "queries/s", "cores": torch.get_num_threads(),
+    # the same oracle on one thread, for one piece of 1/64 of a frame
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    t1 = 0.0
+    for n in [n // 64 for n in BOUNCES]:
+        f, xi = synth.features(n, rng), synth.uniforms(n, rng)
+        t0 = time.perf_counter()
+        lob = onasg.decode(omlp.forward(W, f.T, bf16=True), K)
+        v, _ = onasg.sample(lob, xi.T.astype(np.float64))
+        onasg.mixture_log_pdf(v, lob)
+        t1 += time.perf_counter() - t0
+    torch.set_num_threads(threads)
+    return {"value": round(frames_per_s * sum(BOUNCES), 1), "unit": "queries/s", "cores": threads,
+            "one_thread_query_path_per_s": round(sum(n // 64 for n in BOUNCES) / t1, 1),
             "kind": "oracle", "seconds": round(dt, 2),
             "train_samples_per_s": round(frames_per_s * TRAIN_B, 1),
             "sample": f"{pieces} x 1/{fraction} of a frame (each: {sum(nq)} queries, bounces {nq}, "
                       f"{nt} training samples, one Adam step); FP64 with BF16-rounded MLP operands; "
-                      f"only the oracle's compute is timed"}
+                      f"only the oracle's compute is timed; one_thread_query_path_per_s: the query path "
+                      f"alone (no training) on one thread over 1/64 of a frame's queries"}
 
 
 def main():
@@ -521,6 +546,7 @@ def main():
         out["roofline"] = query_roofline(frame)
         out["records"] = records_legs(frame)
         out["train_step"] = train_leg(frame)
+        out["frame_stages_us"] = stage_legs(frame)
     if not a.no_configs and a.only != "frame":
         out["configs"] = config_legs()
         out["configs"]["paper_default_frame"] = paper_leg(10, not a.no_graph)
