@@ -80,14 +80,6 @@ __device__ __forceinline__ void mfma_rows(const bf16x8* frag, BOp bop, f32x4 (&a
   }
 }
 
-// Copy `bytes` (multiple of 16) from global to LDS with the whole block.
-__device__ __forceinline__ void block_copy_to_lds(void* lds, const void* src, int bytes) {
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(lds);
-  int n = bytes >> 4;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
-}
-
 // Asynchronous copy of `bytes` (multiple of 16) from global memory to LDS
 // with the whole block, through the gfx950 direct-to-LDS load
 // (global_load_lds_dwordx4): every wave moves 1 KiB per instruction, lane i

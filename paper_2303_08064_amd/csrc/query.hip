@@ -85,7 +85,10 @@ void query_kernel(QueryArgs a) {
   static_assert(NB == 1 || PREC == 1, "multi-block passes are BF16 only");
   extern __shared__ __align__(16) unsigned char smem[];
   W* lds = reinterpret_cast<W*>(smem);
-  block_copy_to_lds(lds, a.wpack, a.lds_bytes);
+  // the forward weights by direct-to-LDS loads: every wave's copies are in
+  // flight at once (a register round trip per 16 bytes waited on each load)
+  lds_dma(lds, a.wpack, a.lds_bytes);
+  lds_dma_wait();
   __syncthreads();
   const W* wts = lds;
 
