@@ -41,18 +41,19 @@ __device__ __forceinline__ void dgrad(const void* wl, const float (&dl)[RT][4],
 #pragma unroll
       for (int j = 0; j < 4; ++j) bs[j] = (__bf16)dl[RT - 1][j];
     }
+    // block-major with prefetched fragments (mfma_rows): the chains of the
+    // MTP row tiles interleave instead of waiting on each other
+    f32x4 acc[1][MTP];
+    mfma_rows<MTP, KB, 1>(frag, [&](int, int kb) { return b[kb]; }, acc, lane);
 #pragma unroll
     for (int mt = 0; mt < MTP; ++mt) {
-      f32x4 acc = zero4();
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) acc = mfma_bf16_32(frag[(mt * KB + kb) * 64 + lane], b[kb], acc);
       if constexpr (RT % 2 == 1) {
         const f32x4 sel = mfma_bf16_16(frag_s[mt * 64 + lane], bs, zero4());
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] += sel[i];
+        for (int i = 0; i < 4; ++i) acc[0][mt][i] += sel[i];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[i];
+      for (int i = 0; i < 4; ++i) dp[mt][i] = acc[0][mt][i];
     }
   } else {
     const float* W = reinterpret_cast<const float*>(wl);
@@ -156,6 +157,45 @@ __device__ __forceinline__ void wgrad_own(const S* dst, const S* hst, f32x4 (&ac
   typedef decltype(stage_operand<PREC, S, SP>(dst, 0, 0, 0, 0)) Op;
   const int g = lane >> 4, c = lane & 15;
   constexpr int VB = PREC == 1 ? NV / 32 : NV / 4;
+  if constexpr (PREC == 1) {
+    // BF16: the operands of vertex block vb + 1 are read while block vb is
+    // multiplied (two register sets), so the LDS latency overlaps the MFMAs
+    constexpr int NH_ = O::ROW ? CT : 1, ND = O::ROW ? O::NRW : O::TPW;
+    struct Ops { Op h[NH_]; Op d[ND]; };
+    auto load = [&](int vb, Ops& o) {
+      if constexpr (O::ROW) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) o.h[ct] = stage_operand<PREC, S, SP>(hst, ct, vb, g, c);
+#pragma unroll
+        for (int r = 0; r < O::NRW; ++r)
+          if (O::rt(wave, r * CT) < RT) o.d[r] = stage_operand<PREC, S, SP>(dst, O::rt(wave, r * CT), vb, g, c);
+      } else {
+        o.h[0] = stage_operand<PREC, S, SP>(hst, O::ct(wave, 0), vb, g, c);
+#pragma unroll
+        for (int j = 0; j < O::TPW; ++j)
+          if (O::rt(wave, j) < RT) o.d[j] = stage_operand<PREC, S, SP>(dst, O::rt(wave, j), vb, g, c);
+      }
+    };
+    Ops ops[2];
+    load(0, ops[0]);
+#pragma unroll
+    for (int vb = 0; vb < VB; ++vb) {
+      if (vb + 1 < VB) load(vb + 1, ops[(vb + 1) & 1]);
+      const Ops& o = ops[vb & 1];
+      if constexpr (O::ROW) {
+#pragma unroll
+        for (int r = 0; r < O::NRW; ++r)
+          if (O::rt(wave, r * CT) < RT)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[r * CT + ct] = mfma_bf16_32(o.d[r], o.h[ct], acc[r * CT + ct]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < O::TPW; ++j)
+          if (O::rt(wave, j) < RT) acc[j] = mfma_bf16_32(o.d[j], o.h[0], acc[j]);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int vb = 0; vb < VB; ++vb) {
     if constexpr (O::ROW) {
