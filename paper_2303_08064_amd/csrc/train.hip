@@ -42,7 +42,15 @@ struct TrainCfg {
   typedef Own<MTH, 1, NW> O0;                   // layer 0
   typedef Own<MTH, CTH, NW> OH;                 // hidden layers
   typedef Own<MTO, CTH, NW> OO;                 // output layer
-  static constexpr int stage_elems() { return (RMAX + H) * SP; }
+  // BF16: the hidden layers and layer 0 alternate between two staging
+  // buffers, so a layer's writes never meet the previous layer's weight-
+  // gradient reads and one barrier per layer suffices. The second delta
+  // buffer is rows H..2H-1 of the first where the output layer's delta
+  // (RMAX rows) leaves room, else rows of its own, like the second input
+  // buffer (all BF16 networks fit the 160 KiB of LDS with it).
+  static constexpr bool DB = PREC == 1;
+  static constexpr int EXTRA = DB ? (RMAX >= 2 * H ? H : 2 * H) : 0;   // staging rows of the second buffer
+  static constexpr int stage_elems() { return (RMAX + H + EXTRA) * SP; }
 };
 
 // weights of layer l in LDS (forward and, for l >= 1, backward)
@@ -76,6 +84,9 @@ void train_kernel(TrainArgs a) {
   W* lds = reinterpret_cast<W*>(smem);
   S* dst = reinterpret_cast<S*>(smem + a.lds_bytes);     // delta staging [RMAX][SP]
   S* hst = dst + C::RMAX * SP;                            // input staging [H][SP]
+  // the second staging buffer (C::DB): delta [H][SP], input [H][SP]
+  S* dstB = C::RMAX >= 2 * H ? dst + H * SP : hst + H * SP;
+  S* hstB = C::RMAX >= 2 * H ? hst + H * SP : dstB + H * SP;
   lds_dma(lds, a.wpack, a.lds_bytes);
   lds_dma_wait();
   __syncthreads();
@@ -170,8 +181,14 @@ void train_kernel(TrainArgs a) {
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) prev[mt][i] = h[l - 1][mt][i];
-      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
-      stage_rows<S, MTH, SP>(hst, prev, wave, lane);
+      // the buffers alternate with l (compile-time): a buffer's previous user
+      // is two layers back, whose reads every wave finished before the last
+      // layer's barrier (the output layer's before its second barrier)
+      const bool alt = C::DB && ((NHMAX - 1 - l) & 1);   // folded once the loop unrolls
+      S* const ds = alt ? dstB : dst;
+      S* const hs = alt ? hstB : hst;
+      stage_rows<S, MTH, SP>(ds, dh, wave, lane);
+      stage_rows<S, MTH, SP>(hs, prev, wave, lane);
       float dn[MTH][4];
       dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), dh, dn, lane);
 #pragma unroll
@@ -179,8 +196,8 @@ void train_kernel(TrainArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dn[mt][i] = prev[mt][i] > 0.0f ? dn[mt][i] : 0.0f;
       __syncthreads();
-      wgrad_own<PREC, S, SP, MTH, CTH, NW, NV>(dst, hst, acch[l - 1], wave, lane);
-      __syncthreads();
+      wgrad_own<PREC, S, SP, MTH, CTH, NW, NV>(ds, hs, acch[l - 1], wave, lane);
+      if constexpr (!C::DB) __syncthreads();
 #pragma unroll
       for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
@@ -188,11 +205,14 @@ void train_kernel(TrainArgs a) {
     }
     // ---- layer 0: input = features, constant one, zero padding ----
     {
-      stage_rows<S, MTH, SP>(dst, dh, wave, lane);
-      M::template stage_input<S, SP>(hst, x, wave, lane);
+      constexpr bool alt = C::DB && ((NHMAX - 1) & 1);
+      S* const ds = alt ? dstB : dst;
+      S* const hs = alt ? hstB : hst;
+      stage_rows<S, MTH, SP>(ds, dh, wave, lane);
+      M::template stage_input<S, SP>(hs, x, wave, lane);
       __syncthreads();
-      wgrad_own<PREC, S, SP, MTH, 1, NW, NV>(dst, hst, acc0, wave, lane);
-      __syncthreads();
+      wgrad_own<PREC, S, SP, MTH, 1, NW, NV>(ds, hs, acc0, wave, lane);
+      __syncthreads();   // the next tile's output layer writes both buffers' rows
     }
   }
 
