@@ -189,7 +189,7 @@ __device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], floa
   vz *= inv;
   float ell[KQ];
 #pragma unroll
-  for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe(lb[q], vx, vy, vz, eps).ell;
+  for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe_ell(lb[q], vx, vy, vz, eps);
   return mixture_lse<KQ>(ell);
 }
 

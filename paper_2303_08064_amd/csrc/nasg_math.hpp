@@ -236,6 +236,28 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   return r;
 }
 
+// log c + log G(v) alone (the query's mixture pdf): the same function as
+// eval_lobe without the lobe's y axis. For a unit v and an orthonormal frame
+// X^2 + Y^2 = 1 - (v.z)^2 = (1 - v.z)(1 + v.z) = 4 (1 - u) u, a product of the
+// two cancellation-free terms already at hand; c^2 is capped at 1 against
+// rounding (X^2 and 4 u (1 - u) come from different roundings).
+__device__ __forceinline__ float eval_lobe_ell(const Lobe& L, float vx, float vy, float vz, float eps) {
+  const float dx = vx - L.zx, dy = vy - L.zy, dz = vz - L.zz;
+  const float sx = vx + L.zx, sy = vy + L.zy, sz = vz + L.zz;
+  const float w4 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));   // 4 (1 - u)
+  const float w = 0.25f * w4;
+  const float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  const float lw = log1p_series(-w);
+  const float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
+  const float Lu = fsel(w < 0.0625f, lw, lu);
+  const float X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
+  const float S = w4 * u;
+  const float c2 = fsel(S > 0.0f, fminf(X * X * frcp(S), 1.0f), 0.0f);
+  const float p = 1.0f + eps + L.a * c2;
+  const float lg = fmaf(2.0f * L.lam, expm1f_(p * Lu), (p - 1.0f) * Lu);
+  return fsel(u > 0.0f, L.logc + lg, -INFINITY);
+}
+
 // Euclidean gradient with respect to v of ell = log c + log G (eq. NASG; App.
 // A) at a unit v, through v.z, X = v.x and Y = v.y (the same partials as
 // backward_lobe): d ell/d(v.z) = (2 lam p u^p + p - 1) / (2u) and, with
