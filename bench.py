@@ -241,7 +241,7 @@ def source_hash(names):
     return h.hexdigest()[:16]
 
 
-QUERY_SOURCES = ["query.hip", "mlp.hpp", "nasg_math.hpp", "common.hpp", "kernels.hpp", "layout.hpp"]
+QUERY_SOURCES = ["query.hip", "mlp.hpp", "nasg_math.hpp", "common.hpp", "kernels.hpp", "layout.hpp", "epilogue.hpp"]
 
 
 def committed_traffic():

@@ -34,7 +34,7 @@ __device__ __forceinline__ float logit_lse(const float (&out)[MTO][4]) {
   mx = quad_max(mx);
   float se = 0.0f;
 #pragma unroll
-  for (int q = 0; q < KQ; ++q) se += fexp(alpha[q] - mx);
+  for (int q = 0; q < KQ; ++q) se += fexp_sub(alpha[q], mx);
   se = quad_sum(se);
   return mx + flog(se);
 }
@@ -77,7 +77,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int t = 7 * KQ + q;
-      ea[q] = fexp(out[t >> 2][t & 3] - mx);
+      ea[q] = fexp_sub(out[t >> 2][t & 3], mx);
       se += ea[q];
     }
     se = quad_sum(se);
@@ -122,7 +122,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     const int t7 = 7 * KQ + q;
-    const float r = valid ? fexp(ell[q] - logq) : 0.0f;
+    const float r = valid ? fexp_sub(ell[q], logq) : 0.0f;
     const float Aq = ea[q] * inv_se;
     const float sc = gsq * r;
 #pragma unroll
@@ -168,7 +168,7 @@ __device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], floa
   float se = 0.0f;
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
-    ea[q] = fexp(alpha[q] - mx);
+    ea[q] = fexp_sub(alpha[q], mx);
     se += ea[q];
   }
   se = quad_sum(se);

@@ -182,7 +182,7 @@ __device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
   m = quad_max(m);
   float s = 0.0f;
 #pragma unroll
-  for (int q = 0; q < KQ; ++q) s += fexp(ell[q] - m);
+  for (int q = 0; q < KQ; ++q) s += fexp_sub(ell[q], m);
   s = quad_sum(s);
   return m == -INFINITY ? -INFINITY : m + flog(s);
 }

@@ -23,6 +23,11 @@ constexpr float kLogClamp = 15.0f;                // log lambda, log a in [-15, 
 
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+// e^{a - b} as a log2(e) - b log2(e) in one FMA (the second product is shared
+// across a loop over a with the same b) and one exp2
+__device__ __forceinline__ float fexp_sub(float a, float b) {
+  return __builtin_amdgcn_exp2f(fmaf(a, kLog2e, -(b * kLog2e)));
+}
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -131,10 +136,11 @@ __device__ __forceinline__ void decode_pair(float oc, float os, float& cu, float
 // Gaussian / von Mises-Fisher lobe; the anisotropy output then has zero
 // gradient), 1 the NASG lobe.
 __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X, float amul = 1.0f) {
-  const float e0 = fexp(-fabsf(o[0]));
+  const float h0 = fexp(-0.5f * fabsf(o[0]));        // e^{-|o|/2}
+  const float e0 = h0 * h0;
   const float r0 = frcp(1.0f + e0);
   X.ct = copysignf((1.0f - e0) * r0, o[0]);
-  X.st = 2.0f * fsqrt(e0) * r0;                      // sech(o/2) = sqrt(1 - tanh^2)
+  X.st = 2.0f * h0 * r0;                             // sech(o/2) = sqrt(1 - tanh^2)
   decode_pair(o[2], o[1], X.cp, X.sp, X.inv_np, X.h2, X.h1);
   decode_pair(o[4], o[3], X.ctau, X.stau, X.inv_nt, X.h4, X.h3);
   L.zx = X.cp * X.st;
@@ -166,10 +172,11 @@ __device__ __forceinline__ float one_minus_exp_neg(float ao) {
 // log K folded into log c by the caller. Returns log K.
 __device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, Lobe& L, float amul = 1.0f) {
   // theta: cos = tanh(o0/2) (absolute accuracy suffices), sin = sech(o0/2)
-  const float e0 = fexp(-fabsf(o[0]));
+  const float h0 = fexp(-0.5f * fabsf(o[0]));        // e^{-|o|/2}: sin without a square root
+  const float e0 = h0 * h0;
   const float r0 = frcp(1.0f + e0);
   const float ct = copysignf((1.0f - e0) * r0, o[0]);
-  const float st = 2.0f * fsqrt(e0) * r0;
+  const float st = 2.0f * h0 * r0;
   const float m1 = one_minus_exp_neg(fabsf(o[1])), m2 = one_minus_exp_neg(fabsf(o[2]));
   const float m3 = one_minus_exp_neg(fabsf(o[3])), m4 = one_minus_exp_neg(fabsf(o[4]));
   float cp, sp, ctau, stau, inv;
