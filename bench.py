@@ -261,11 +261,25 @@ def committed_traffic():
     return int(fields["hbm_bytes_per_launch"])
 
 
-def query_roofline(frame, reps=20):
+def query_launch_ms(frame, warm=100, reps=20):
+    """Average duration of the 2^20-vertex query launch: `warm` launches
+    first (the GPU's clocks settle under load), then `reps` timed by HIP
+    events on the launching stream. `--only query` runs exactly this, so the
+    rocprofv3 kernel trace of that command averages the same launches."""
     import torch
     g = frame.guide
     (f, xi), (d, p) = frame.q_in[0], frame.q_out[0]
-    ms = kernel_avg_ms(lambda: g.query(f, xi, dir_out=d, pdf_out=p), reps)
+    run = lambda: g.query(f, xi, dir_out=d, pdf_out=p)
+    for _ in range(warm):
+        run()
+    torch.cuda.synchronize()
+    return kernel_avg_ms(run, reps)
+
+
+def query_roofline(frame, reps=20):
+    import torch
+    (f, xi) = frame.q_in[0]
+    ms = query_launch_ms(frame, reps=reps)
     n = f.shape[1]
     ops = query_valu_ops(K) * n
     achieved = ops / (ms * 1e-3) / 1e12
@@ -475,11 +489,8 @@ def main():
     torch.cuda.set_device(0)
     frame = Frame("bf16")
     if a.only == "query":
-        (f, xi), (d, p) = frame.q_in[0], frame.q_out[0]
-        for _ in range(a.steps):
-            frame.guide.query(f, xi, dir_out=d, pdf_out=p)
-        torch.cuda.synchronize()
-        print(json.dumps({"only": "query", "steps": a.steps}))
+        ms = query_launch_ms(frame, reps=a.steps)
+        print(json.dumps({"only": "query", "steps": a.steps, "avg_ms": round(ms, 4)}))
         return
     if a.only == "copy":
         # a plain device copy of known size, to scale the HBM byte counters
