@@ -74,38 +74,41 @@ __device__ __forceinline__ void dgrad(const void* wl, const float (&dl)[RT][4],
   }
 }
 
+// One row tile of BF16 staging, [row][vertex] at `tile` (its row 0, the
+// wave's vertex column 0): lane (g, c) holds rows 4g..4g+3 of vertex c as
+// two packed words, w0 (rows 4g, 4g+1) and w1 (rows 4g+2, 4g+3). Lanes c and
+// c^1 (neighbouring vertices) swap half of them through one DPP move, so
+// each writes two rows of both vertices as two 4-byte stores (the even lane
+// rows 4g, 4g+1, the odd lane rows 4g+2, 4g+3; one ds_write2_b32) instead
+// of four 2-byte stores.
+template <int SP>
+__device__ __forceinline__ void stage_tile_bf16(__bf16* tile, uint32_t w0, uint32_t w1, int g, int c) {
+  const bool odd = c & 1;
+  const uint32_t send = odd ? w0 : w1;   // the rows the partner writes
+  const uint32_t mine = odd ? w1 : w0;
+  // quad_perm [1, 0, 3, 2]: the value of lane c^1
+  const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
+  // v_perm_b32 byte selectors over (recv: bytes 4..7, mine: bytes 0..3):
+  // even lane (recv = vertex c+1) [mine.lo, recv.lo], [mine.hi, recv.hi];
+  // odd lane (recv = vertex c-1) [recv.lo, mine.lo], [recv.hi, mine.hi]
+  __bf16* const p = tile + (4 * g + (odd ? 2 : 0)) * SP + (c & ~1);
+  *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(recv, mine, odd ? 0x01000504u : 0x05040100u);
+  *reinterpret_cast<uint32_t*>(p + SP) = __builtin_amdgcn_perm(recv, mine, odd ? 0x03020706u : 0x07060302u);
+}
+
 // Write a wave's accumulator-layout block [RT*16 rows][16 vertices] into the
-// staging buffer at vertex column wave*16.
-//
-// BF16: lanes c and c^1 (neighbouring vertices) swap half of their rows
-// through one DPP move, so that each writes two rows of both vertices as two
-// 4-byte stores (the even lane rows 4g, 4g+1, the odd lane rows 4g+2, 4g+3)
-// instead of four 2-byte stores: half the LDS write instructions.
+// staging buffer at vertex column wave*16 (BF16 through stage_tile_bf16).
 template <typename S, int RT, int SP>
 __device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int wave, int lane) {
   const int g = lane >> 4, c = lane & 15;
   if constexpr (sizeof(S) == 2) {
     typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
     typedef __attribute__((ext_vector_type(2))) float f32x2;
-    const bool odd = c & 1;
-    // v_perm_b32 byte selectors over (recv: bytes 4..7, mine: bytes 0..3):
-    // even lane (mine = vertex c, recv = vertex c+1): [mine.lo, recv.lo] and
-    // [mine.hi, recv.hi]; odd lane (recv = vertex c-1): [recv.lo, mine.lo]
-    // and [recv.hi, mine.hi]
-    const uint32_t sel_lo = odd ? 0x01000504u : 0x05040100u;
-    const uint32_t sel_hi = odd ? 0x03020706u : 0x07060302u;
-    S* const base = buf + (4 * g + (odd ? 2 : 0)) * SP + wave * 16 + (c & ~1);
 #pragma unroll
     for (int mt = 0; mt < RT; ++mt) {
       const uint32_t w0 = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){x[mt][0], x[mt][1]}, bf16x2));
       const uint32_t w1 = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){x[mt][2], x[mt][3]}, bf16x2));
-      const uint32_t send = odd ? w0 : w1;   // the rows the partner writes
-      const uint32_t mine = odd ? w1 : w0;
-      // quad_perm [1, 0, 3, 2]: the value of lane c^1
-      const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
-      S* const p = base + mt * 16 * SP;
-      *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(recv, mine, sel_lo);
-      *reinterpret_cast<uint32_t*>(p + SP) = __builtin_amdgcn_perm(recv, mine, sel_hi);
+      stage_tile_bf16<SP>(reinterpret_cast<__bf16*>(buf) + mt * 16 * SP + wave * 16, w0, w1, g, c);
     }
   } else {
 #pragma unroll

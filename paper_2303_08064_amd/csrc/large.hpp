@@ -83,14 +83,9 @@ struct Pk {
   template <int SP, int MT0 = 0, int NMT = RT>
   __device__ __forceinline__ void stage(__bf16* buf, int wave, int lane) const {
     const int g = lane >> 4, c = lane & 15;
-    unsigned short* b = reinterpret_cast<unsigned short*>(buf) + 4 * g * SP + wave * 16 + c;
 #pragma unroll
     for (int mt = 0; mt < NMT; ++mt)
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        b[(mt * 16 + 2 * k) * SP] = (unsigned short)(p[MT0 + mt][k] & 0xffffu);
-        b[(mt * 16 + 2 * k + 1) * SP] = (unsigned short)(p[MT0 + mt][k] >> 16);
-      }
+      stage_tile_bf16<SP>(buf + mt * 16 * SP + wave * 16, p[MT0 + mt][0], p[MT0 + mt][1], g, c);
   }
 };
 
