@@ -28,6 +28,23 @@ __device__ __forceinline__ float quad_sum(float x) {
   x += __shfl_xor(x, 16);
   return x + __shfl_xor(x, 32);
 }
+// The same reductions by the gfx950 lane swaps (VALU, no LDS round trip):
+// v_permlane16_swap of x with itself leaves x and its xor-16 partner in the
+// two results of every lane, v_permlane32_swap the xor-32 partner; the
+// operations are the same commutative pairs as above, so the results are
+// bitwise the same.
+__device__ __forceinline__ float xchg_max(float x) {
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+__device__ __forceinline__ float xchg_sum(float x) {
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
 __device__ __forceinline__ int quad_min_i(int x) {
   x = min(x, __shfl_xor(x, 16));
   return min(x, __shfl_xor(x, 32));

@@ -72,7 +72,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
       const int t = 7 * KQ + q;
       mx = fmaxf(mx, out[t >> 2][t & 3]);
     }
-    mx = quad_max(mx);
+    mx = xchg_max(mx);
     float se = 0.0f;
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
@@ -80,7 +80,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
       ea[q] = fexp_sub(out[t >> 2][t & 3], mx);
       se += ea[q];
     }
-    se = quad_sum(se);
+    se = xchg_sum(se);
     lse = mx + flog(se);
     inv_se = frcp(se);
   }
@@ -103,7 +103,7 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
       dl[t >> 2][t & 3] = gq[p];
     }
   }
-  const float logq = mixture_lse<KQ>(ell);
+  const float logq = mixture_lse<KQ, true>(ell);
   float lterm = logq, gsq = gs;
   if constexpr (S == 1) {
     const int c = lane_id() & 15;

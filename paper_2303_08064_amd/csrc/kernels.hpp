@@ -174,16 +174,18 @@ __device__ __forceinline__ Lobe broadcast_lobe(const Lobe (&lb)[KQ], int k, int 
 }
 
 // log sum_k exp(ell_k) over the lane's KQ lobes and the vertex's 4 lanes.
-template <int KQ>
+// XCHG: the cross-lane steps by lane swaps (xchg_max/xchg_sum) instead of
+// LDS permutes.
+template <int KQ, bool XCHG = false>
 __device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
   float m = ell[0];
 #pragma unroll
   for (int q = 1; q < KQ; ++q) m = fmaxf(m, ell[q]);
-  m = quad_max(m);
+  m = XCHG ? xchg_max(m) : quad_max(m);
   float s = 0.0f;
 #pragma unroll
   for (int q = 0; q < KQ; ++q) s += fexp_sub(ell[q], m);
-  s = quad_sum(s);
+  s = XCHG ? xchg_sum(s) : quad_sum(s);
   return m == -INFINITY ? -INFINITY : m + flog(s);
 }
 
