@@ -118,6 +118,48 @@ __device__ __forceinline__ void stage_rows(S* buf, const float (&x)[RT][4], int 
   }
 }
 
+// BF16 rows of a block packed in pairs (as the MFMA operands hold them):
+// w[mt][0] = rows mt*16 + 4g, + 4g + 1 and w[mt][1] = rows + 4g + 2, + 4g + 3
+// of vertex c, low half first; rounded to nearest even.
+template <int RT>
+__device__ __forceinline__ void pack_rows(const float (&x)[RT][4], uint32_t (&w)[RT][2]) {
+  typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+  typedef __attribute__((ext_vector_type(2))) float f32x2;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      w[mt][k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){x[mt][2 * k], x[mt][2 * k + 1]}, bf16x2));
+}
+
+// Packed rows into the staging buffer at vertex column wave*16.
+template <int RT, int SP>
+__device__ __forceinline__ void stage_words(__bf16* buf, const uint32_t (&w)[RT][2], int wave, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt) stage_tile_bf16<SP>(buf + mt * 16 * SP + wave * 16, w[mt][0], w[mt][1], g, c);
+}
+
+// dgrad (BF16) with the deltas already packed: the packed words are the B
+// operands as they are (an even number of row tiles, no selection tile).
+template <int H, int RT>
+__device__ __forceinline__ void dgrad_words(const void* wl, const uint32_t (&dw)[RT][2], float (&dp)[H / 16][4],
+                                            int lane) {
+  static_assert(RT % 2 == 0, "whole 32-wide blocks");
+  constexpr int MTP = H / 16, KB = RT / 2;
+  typedef __attribute__((ext_vector_type(4))) uint32_t u32x4_;
+  bf16x8 b[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+    b[kb] = __builtin_bit_cast(bf16x8, u32x4_{dw[2 * kb][0], dw[2 * kb][1], dw[2 * kb + 1][0], dw[2 * kb + 1][1]});
+  f32x4 acc[1][MTP];
+  mfma_rows<MTP, KB, 1>(reinterpret_cast<const bf16x8*>(wl), [&](int, int kb) { return b[kb]; }, acc, lane);
+#pragma unroll
+  for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dp[mt][i] = acc[0][mt][i];
+}
+
 // acc[rt][ct] += D[rows rt*16..][v] * Hs[cols ct*16..][v]^T over the NV staged vertices
 template <int PREC, typename S, int SP, int NR, int NC, int NV = kWGV>
 __device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const int (&rt)[NR], int nrt,

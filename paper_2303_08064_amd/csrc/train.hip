@@ -159,15 +159,30 @@ void train_kernel(TrainArgs a) {
     }
 
     // ---- MLP backward: output layer ----
+    // BF16: the deltas below the output layer travel as packed words, the
+    // staging and the next dgrad's B operands alike (one conversion where
+    // there were two); FP32 keeps floats
     float dh[MTH][4];
+    uint32_t dw[MTH][2];
     {
       stage_rows<S, MTO, SP>(dst, dl, wave, lane);
-      stage_rows<S, MTH, SP>(hst, last, wave, lane);
       dgrad<H, K, PREC, MTO>(TL::bwd(lds, nh, nh), dl, dh, lane);
+      if constexpr (PREC == 1) {
+        uint32_t aw[MTH][2];
+        pack_rows(last, aw);
+        stage_words<MTH, SP>(hst, aw, wave, lane);
 #pragma unroll
-      for (int mt = 0; mt < MTH; ++mt)
+        for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
+          for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
+        pack_rows(dh, dw);
+      } else {
+        stage_rows<S, MTH, SP>(hst, last, wave, lane);
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
+      }
       __syncthreads();
       wgrad_own<PREC, S, SP, MTO, CTH, NW, NV>(dst, hst, acco, wave, lane);
       __syncthreads();
@@ -176,39 +191,45 @@ void train_kernel(TrainArgs a) {
 #pragma unroll
     for (int l = NHMAX - 1; l >= 1; --l) {
       if (l >= nh) continue;
-      float prev[MTH][4];
-#pragma unroll
-      for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) prev[mt][i] = h[l - 1][mt][i];
       // the buffers alternate with l (compile-time): a buffer's previous user
       // is two layers back, whose reads every wave finished before the last
       // layer's barrier (the output layer's before its second barrier)
       const bool alt = C::DB && ((NHMAX - 1 - l) & 1);   // folded once the loop unrolls
       S* const ds = alt ? dstB : dst;
       S* const hs = alt ? hstB : hst;
-      stage_rows<S, MTH, SP>(ds, dh, wave, lane);
-      stage_rows<S, MTH, SP>(hs, prev, wave, lane);
       float dn[MTH][4];
-      dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), dh, dn, lane);
+      if constexpr (PREC == 1) {
+        uint32_t aw[MTH][2];
+        pack_rows(h[l - 1], aw);
+        stage_words<MTH, SP>(ds, dw, wave, lane);
+        stage_words<MTH, SP>(hs, aw, wave, lane);
+        dgrad_words<H, MTH>(TL::bwd(lds, l, nh), dw, dn, lane);
 #pragma unroll
-      for (int mt = 0; mt < MTH; ++mt)
+        for (int mt = 0; mt < MTH; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dn[mt][i] = prev[mt][i] > 0.0f ? dn[mt][i] : 0.0f;
+          for (int i = 0; i < 4; ++i) dn[mt][i] = h[l - 1][mt][i] > 0.0f ? dn[mt][i] : 0.0f;
+        pack_rows(dn, dw);
+      } else {
+        const float (&prev)[MTH][4] = h[l - 1];
+        stage_rows<S, MTH, SP>(ds, dh, wave, lane);
+        stage_rows<S, MTH, SP>(hs, prev, wave, lane);
+        dgrad<H, K, PREC, MTH>(TL::bwd(lds, l, nh), dh, dn, lane);
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dh[mt][i] = prev[mt][i] > 0.0f ? dn[mt][i] : 0.0f;
+      }
       __syncthreads();
       wgrad_own<PREC, S, SP, MTH, CTH, NW, NV>(ds, hs, acch[l - 1], wave, lane);
       if constexpr (!C::DB) __syncthreads();
-#pragma unroll
-      for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) dh[mt][i] = dn[mt][i];
     }
     // ---- layer 0: input = features, constant one, zero padding ----
     {
       constexpr bool alt = C::DB && ((NHMAX - 1) & 1);
       S* const ds = alt ? dstB : dst;
       S* const hs = alt ? hstB : hst;
-      stage_rows<S, MTH, SP>(ds, dh, wave, lane);
+      if constexpr (PREC == 1) stage_words<MTH, SP>(ds, dw, wave, lane);
+      else stage_rows<S, MTH, SP>(ds, dh, wave, lane);
       M::template stage_input<S, SP>(hs, x, wave, lane);
       __syncthreads();
       wgrad_own<PREC, S, SP, MTH, 1, NW, NV>(ds, hs, acc0, wave, lane);
