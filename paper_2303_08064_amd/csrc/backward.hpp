@@ -132,6 +132,20 @@ __device__ __forceinline__ void pack_rows(const float (&x)[RT][4], uint32_t (&w)
       w[mt][k] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){x[mt][2 * k], x[mt][2 * k + 1]}, bf16x2));
 }
 
+// d *= (h != 0) per BF16 half: the ReLU derivative, h being packed ReLU
+// outputs (non-negative, so min(h, 1) as a 16-bit integer is the indicator)
+template <int RT>
+__device__ __forceinline__ void mask_rows(uint32_t (&d)[RT][2], const uint32_t (&h)[RT][2]) {
+  typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const u16x2 ind = __builtin_elementwise_min(__builtin_bit_cast(u16x2, h[mt][k]), (u16x2)1);
+      d[mt][k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, d[mt][k]) * ind);
+    }
+}
+
 // Packed rows into the staging buffer at vertex column wave*16.
 template <int RT, int SP>
 __device__ __forceinline__ void stage_words(__bf16* buf, const uint32_t (&w)[RT][2], int wave, int lane) {

@@ -417,6 +417,40 @@ struct Forward {
     M::template gemm<MTO>(layer_ptr(lds, nh, nh), last, out, lane);
   }
 
+  // BF16 forward keeping the hidden activations packed: hw[l] receives layer
+  // l's ReLU outputs as BF16 pairs (word k of row tile mt: rows mt*16 + 4g +
+  // 2k, + 1 of vertex c, low half first), exactly the operands the next layer
+  // read; lastw the pairs the output layer reads (hw[nh-1]). Same values as
+  // run() rounded to BF16.
+  __device__ __forceinline__ static void run_packed(const W* lds, int nh, const typename M::Input& x,
+                                                    uint32_t (&hw)[NHMAX][M::MTH][2], uint32_t (&lastw)[M::MTH][2],
+                                                    float (&out)[MTO][4], int lane) {
+    static_assert(PREC == 1, "BF16 only");
+    typedef __attribute__((ext_vector_type(4))) uint32_t u32x4_;
+    float y[M::MTH][4];
+    bf16x8 b[M::KBH];
+    auto keep = [&](uint32_t (&w)[M::MTH][2]) {
+#pragma unroll
+      for (int kb = 0; kb < M::KBH; ++kb) {
+        const u32x4_ q = __builtin_bit_cast(u32x4_, b[kb]);
+        w[2 * kb][0] = q[0]; w[2 * kb][1] = q[1]; w[2 * kb + 1][0] = q[2]; w[2 * kb + 1][1] = q[3];
+      }
+    };
+    M::layer0_linear(layer_ptr(lds, 0, nh), x, y, lane);
+    M::relu_operands(y, b);
+    keep(hw[0]);
+#pragma unroll
+    for (int l = 1; l < NHMAX; ++l) {
+      if (l < nh) {
+        M::template gemm_op<M::MTH>(layer_ptr(lds, l, nh), b, y, lane);
+        M::relu_operands(y, b);
+        keep(hw[l]);
+      }
+    }
+    keep(lastw);
+    M::template gemm_op<MTO>(layer_ptr(lds, nh, nh), b, out, lane);
+  }
+
   // BF16 query forward of NB vertex blocks sharing every weight fragment read
   template <int NB, bool BM>
   __device__ __forceinline__ static void run_query_nb(const W* lds, int nh, const typename M::Input (&x)[NB],

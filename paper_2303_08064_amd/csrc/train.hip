@@ -138,10 +138,16 @@ void train_kernel(TrainArgs a) {
     if (tile + gridDim.x < n_tiles) nxt = load_in((tile + gridDim.x) * NV + wave * 16 + c);
     // ---- forward (recomputed) ----
     const typename M::Input x = cur.x;
-    float h[NHMAX][MTH][4];
-    float last[MTH][4];
+    // BF16 keeps the activations packed (hw, lastw), FP32 as floats (h, last)
+    constexpr int NHF = PREC == 1 ? 1 : NHMAX, MTF = PREC == 1 ? 1 : MTH;
+    constexpr int NHP = PREC == 1 ? NHMAX : 1, MTP_ = PREC == 1 ? MTH : 1;
+    float h[NHF][MTF][4];
+    float last[MTF][4];
+    uint32_t hw[NHP][MTP_][2];
+    uint32_t lastw[MTP_][2];
     float out[MTO][4];
-    Forward<H, K, PREC, NHMAX, SEL>::run(lds, nh, x, h, last, out, lane);
+    if constexpr (PREC == 1) Forward<H, K, PREC, NHMAX, SEL>::run_packed(lds, nh, x, hw, lastw, out, lane);
+    else Forward<H, K, PREC, NHMAX, SEL>::run(lds, nh, x, h, last, out, lane);
 
     // ---- weighted NLL and its gradient w.r.t. the raw outputs ----
     float vx = cur.dx, vy = cur.dy, vz = cur.dz;
@@ -159,23 +165,18 @@ void train_kernel(TrainArgs a) {
     }
 
     // ---- MLP backward: output layer ----
-    // BF16: the deltas below the output layer travel as packed words, the
-    // staging and the next dgrad's B operands alike (one conversion where
-    // there were two); FP32 keeps floats
+    // BF16: activations and the deltas below the output layer travel as
+    // packed words, the staging and the next dgrad's B operands alike, the
+    // ReLU derivative a 16-bit mask on them (mask_rows); FP32 keeps floats
     float dh[MTH][4];
     uint32_t dw[MTH][2];
     {
       stage_rows<S, MTO, SP>(dst, dl, wave, lane);
       dgrad<H, K, PREC, MTO>(TL::bwd(lds, nh, nh), dl, dh, lane);
       if constexpr (PREC == 1) {
-        uint32_t aw[MTH][2];
-        pack_rows(last, aw);
-        stage_words<MTH, SP>(hst, aw, wave, lane);
-#pragma unroll
-        for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) dh[mt][i] = last[mt][i] > 0.0f ? dh[mt][i] : 0.0f;
+        stage_words<MTH, SP>(hst, lastw, wave, lane);
         pack_rows(dh, dw);
+        mask_rows(dw, lastw);
       } else {
         stage_rows<S, MTH, SP>(hst, last, wave, lane);
 #pragma unroll
@@ -199,16 +200,11 @@ void train_kernel(TrainArgs a) {
       S* const hs = alt ? hstB : hst;
       float dn[MTH][4];
       if constexpr (PREC == 1) {
-        uint32_t aw[MTH][2];
-        pack_rows(h[l - 1], aw);
         stage_words<MTH, SP>(ds, dw, wave, lane);
-        stage_words<MTH, SP>(hs, aw, wave, lane);
+        stage_words<MTH, SP>(hs, hw[l - 1], wave, lane);
         dgrad_words<H, MTH>(TL::bwd(lds, l, nh), dw, dn, lane);
-#pragma unroll
-        for (int mt = 0; mt < MTH; ++mt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) dn[mt][i] = h[l - 1][mt][i] > 0.0f ? dn[mt][i] : 0.0f;
         pack_rows(dn, dw);
+        mask_rows(dw, hw[l - 1]);
       } else {
         const float (&prev)[MTH][4] = h[l - 1];
         stage_rows<S, MTH, SP>(ds, dh, wave, lane);
