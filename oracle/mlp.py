@@ -50,6 +50,20 @@ def flatten(mats):
     return torch.cat([m.reshape(-1) for m in mats])
 
 
+class _RoundGradBf16(torch.autograd.Function):
+    """Identity in the forward pass; in the backward pass the incoming
+    gradient is rounded to float32 and then to the nearest bfloat16 (ties to
+    even): a backward operand (a delta) held in BF16."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return t.view_as(t)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.to(torch.float32).to(torch.bfloat16).to(F64)
+
+
 def round_bf16(t):
     """Round to the nearest bfloat16 (ties to even) through float32.
 
@@ -74,12 +88,17 @@ def network_input(feat, in_cols):
 def forward(weights, feat, bf16=False, return_pre=False):
     """Raw outputs [B, 8K (+1)] for raw features [B, 9].
 
-    bf16=True emulates a BF16 GEMM with wide accumulation: every weight and
-    every layer input (the features or their encoding, and the constant one)
-    is rounded
-    to bfloat16, products are summed in float64, and a hidden pre-activation
-    is rounded to float32 before the ReLU and the next rounding to bfloat16.
-    The last layer's result is not rounded.
+    bf16=True emulates BF16 GEMMs with wide accumulation, forward and
+    backward. Forward: every weight and every layer input (the features or
+    their encoding, and the constant one) is rounded to bfloat16, products
+    are summed in float64, and a hidden pre-activation is rounded to float32
+    before the ReLU and the next rounding to bfloat16; the last layer's
+    result is not rounded. Backward (under autograd): the delta of every
+    layer, dL/d(pre-activation) including dL/d(raw outputs), is rounded to
+    float32 and then to bfloat16 before it is used, both for that layer's
+    weight gradient (delta times the layer's BF16 input, summed in float64)
+    and for the delta of the layer below (the BF16 weights transposed times
+    the delta, masked by the ReLU derivative).
     """
     h = network_input(feat, torch.as_tensor(weights[0]).shape[1])
     pre = []
@@ -90,6 +109,8 @@ def forward(weights, feat, bf16=False, return_pre=False):
             W = round_bf16(W)
             h = round_bf16(h)
         y = h @ W.T
+        if bf16:
+            y = _RoundGradBf16.apply(y)
         pre.append(y)
         if l < n - 1:
             if bf16:

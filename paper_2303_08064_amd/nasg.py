@@ -21,12 +21,38 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _rows(t, rows, name):
-    if t.dtype != torch.float32 or not t.is_cuda:
+def _rows(t, rows, name, device=None):
+    """(B, ld) of a [rows, B] float32 device tensor with unit stride along B;
+    raises before any launch when the tensor cannot be read or written as such."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
         raise TypeError(f"{name} must be a float32 CUDA tensor")
-    if t.dim() != 2 or t.shape[0] != rows or t.stride(1) != 1:
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the guide on {device}")
+    if t.dim() != 2 or t.shape[0] != rows or (t.shape[1] > 1 and t.stride(1) != 1):
         raise ValueError(f"{name} must be [{rows}, B] with unit stride along B")
-    return t.shape[1], t.stride(0)
+    ld = t.stride(0) if rows > 1 else max(t.shape[1], 1)
+    if ld < t.shape[1]:
+        raise ValueError(f"{name}: rows overlap (leading dimension {ld} < B = {t.shape[1]})")
+    return t.shape[1], ld
+
+
+def _out_rows(t, rows, B, ld, name, device):
+    """Check a caller-supplied [rows][ld] output: the kernels write entries
+    0..B-1 of each row at row * ld, so its rows must have the input's stride."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or t.device != device:
+        raise TypeError(f"{name} must be a float32 tensor on {device}")
+    if t.dim() != 2 or t.shape[0] != rows or t.shape[1] < B or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be [{rows}, >= {B}] with unit stride along B")
+    if rows > 1 and t.stride(0) != ld:
+        raise ValueError(f"{name} must have leading dimension {ld} (the input's), not {t.stride(0)}")
+
+
+def _vec(t, n, name, device):
+    """Check a float32 device vector of at least n contiguous elements."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or t.device != device:
+        raise TypeError(f"{name} must be a float32 tensor on {device}")
+    if t.dim() != 1 or t.numel() < n or (t.numel() > 1 and t.stride(0) != 1):
+        raise ValueError(f"{name} must be a contiguous 1-D tensor of at least {n} elements")
 
 
 def record_elems(n_lobes, B):
@@ -109,11 +135,49 @@ class NasgGuide:
         """Refresh the kernel-layout weights after writing self.w directly."""
         check(self.lib.nasg_pack(self._ctx, self._stream()))
 
+    # -- checkpoints -------------------------------------------------------------
+    STATE_KEYS = ("w", "adam_m", "adam_v", "step", "flags")
+
+    def state_dict(self):
+        """Host copies of the training state: FP32 master weights, Adam
+        moments, the step counter and the flags. Together with the
+        configuration they determine every later call bit for bit."""
+        torch.cuda.current_stream().synchronize()
+        return {k: getattr(self, k).detach().cpu().clone() for k in self.STATE_KEYS}
+
+    def load_state_dict(self, sd):
+        """Restore a state_dict() of a guide with the same configuration and
+        refresh the kernel-layout copy of the weights."""
+        for k in self.STATE_KEYS:
+            dst, src = getattr(self, k), sd[k]
+            if src.shape != dst.shape or src.dtype != dst.dtype:
+                raise ValueError(f"{k}: expected {tuple(dst.shape)} {dst.dtype}, got {tuple(src.shape)} {src.dtype}")
+        with torch.no_grad():
+            for k in self.STATE_KEYS:
+                getattr(self, k).copy_(sd[k])
+        self.repack()
+
     # -- calls -----------------------------------------------------------------
+    # Every call checks its tensors (dtype, device, shape, leading dimension,
+    # size) and raises before anything is launched: the library receives bare
+    # pointers and cannot tell a short or host buffer from a good one.
+    @property
+    def device(self):
+        return self.w.device
+
+    def _rec(self, rec, B):
+        n = record_elems(self.n_lobes, B)
+        if not isinstance(rec, torch.Tensor) or rec.dtype != torch.float32 or rec.device != self.device:
+            raise TypeError(f"rec must be a float32 tensor on {self.device}")
+        if not rec.is_contiguous() or rec.numel() < n:
+            raise ValueError(f"rec must be contiguous with at least {n} floats (records of {B} vertices)")
+
     def forward_raw(self, feat, out=None):
-        B, ld = _rows(feat, 9, "feat")
+        B, ld = _rows(feat, 9, "feat", self.device)
         if out is None:
-            out = torch.empty(self.n_out, max(ld, 1), dtype=torch.float32, device=feat.device)
+            out = torch.empty(self.n_out, max(ld, 1), dtype=torch.float32, device=self.device)
+        else:
+            _out_rows(out, self.n_out, B, ld, "out", self.device)
         check(self.lib.nasg_forward(self._ctx, _ptr(feat), ld, B, _ptr(out), self._stream()))
         return out[:, :B]
 
@@ -124,19 +188,27 @@ class NasgGuide:
     def query(self, feat, xi, dir_out=None, pdf_out=None, rec_out=None, records=False, sel_out=None):
         """(directions [3, B], pdf [B]) plus the records buffer when requested;
         sel_out (a [B] tensor, selection networks only) receives c."""
-        B, ld = _rows(feat, 9, "feat")
-        Bx, ldx = _rows(xi, 4, "xi")
+        dev = self.device
+        B, ld = _rows(feat, 9, "feat", dev)
+        Bx, ldx = _rows(xi, 4, "xi", dev)
         if Bx != B or ldx != ld:
             raise ValueError("xi must match feat in B and leading dimension")
-        dev = feat.device
         if dir_out is None:
             dir_out = torch.empty(3, max(ld, 1), dtype=torch.float32, device=dev)
+        else:
+            _out_rows(dir_out, 3, B, ld, "dir_out", dev)
         if pdf_out is None:
             pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        else:
+            _vec(pdf_out, B, "pdf_out", dev)
         if records and rec_out is None:
             rec_out = torch.empty(max(record_elems(self.n_lobes, B), 1), dtype=torch.float32, device=dev)
-        if sel_out is not None and (sel_out.dtype != torch.float32 or sel_out.numel() < B):
-            raise ValueError("sel_out must be a float32 tensor of at least B elements")
+        elif rec_out is not None:
+            self._rec(rec_out, B)
+        if sel_out is not None:
+            if not self.selection:
+                raise ValueError("sel_out needs a network with the selection output")
+            _vec(sel_out, B, "sel_out", dev)
         check(self.lib.nasg_query(self._ctx, _ptr(feat), _ptr(xi), ld, B, _ptr(dir_out), _ptr(pdf_out),
                                   _ptr(sel_out), _ptr(rec_out), self._stream()))
         if rec_out is not None:
@@ -144,45 +216,62 @@ class NasgGuide:
         return dir_out[:, :B], pdf_out[:B]
 
     def pdf(self, rec, dirs, pdf_out=None):
-        B, ld = _rows(dirs, 3, "dirs")
+        dev = self.device
+        B, ld = _rows(dirs, 3, "dirs", dev)
+        self._rec(rec, B)
         if pdf_out is None:
-            pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dirs.device)
+            pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        else:
+            _vec(pdf_out, B, "pdf_out", dev)
         check(self.lib.nasg_pdf(self._ctx, _ptr(rec), _ptr(dirs), ld, B, _ptr(pdf_out), self._stream()))
         return pdf_out[:B]
 
     def pdf_grad(self, rec, dirs, pdf_out=None, grad_out=None):
         """(pdf [B], gradient of log pdf on the sphere [3, B]) at dirs."""
-        B, ld = _rows(dirs, 3, "dirs")
-        dev = dirs.device
+        dev = self.device
+        B, ld = _rows(dirs, 3, "dirs", dev)
+        self._rec(rec, B)
         if pdf_out is None:
             pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        else:
+            _vec(pdf_out, B, "pdf_out", dev)
         if grad_out is None:
             grad_out = torch.empty(3, max(ld, 1), dtype=torch.float32, device=dev)
+        else:
+            _out_rows(grad_out, 3, B, ld, "grad_out", dev)
         check(self.lib.nasg_pdf_grad(self._ctx, _ptr(rec), _ptr(dirs), ld, B, _ptr(pdf_out), _ptr(grad_out),
                                      self._stream()))
         return pdf_out[:B], grad_out[:, :B]
 
     def sample(self, rec, xi, dir_out=None, pdf_out=None):
-        B, ld = _rows(xi, 4, "xi")
-        dev = xi.device
+        dev = self.device
+        B, ld = _rows(xi, 4, "xi", dev)
+        self._rec(rec, B)
         if dir_out is None:
             dir_out = torch.empty(3, max(ld, 1), dtype=torch.float32, device=dev)
+        else:
+            _out_rows(dir_out, 3, B, ld, "dir_out", dev)
         if pdf_out is None:
             pdf_out = torch.empty(max(B, 1), dtype=torch.float32, device=dev)
+        else:
+            _vec(pdf_out, B, "pdf_out", dev)
         check(self.lib.nasg_sample(self._ctx, _ptr(rec), _ptr(xi), ld, B, _ptr(dir_out), _ptr(pdf_out),
                                    self._stream()))
         return dir_out[:, :B], pdf_out[:B]
 
     def _train_args(self, feat, dirs, w, bsdf_pdf):
-        B, ld = _rows(feat, 9, "feat")
-        Bd, ldd = _rows(dirs, 3, "dirs")
+        dev = self.device
+        B, ld = _rows(feat, 9, "feat", dev)
+        Bd, ldd = _rows(dirs, 3, "dirs", dev)
         if Bd != B or ldd != ld:
             raise ValueError("dirs must match feat in B and leading dimension")
-        for t, name in ((w, "w"), (bsdf_pdf, "bsdf_pdf")):
-            if t is None:
-                continue
-            if t.dtype != torch.float32 or t.dim() != 1 or t.shape[0] < B or t.stride(0) != 1:
-                raise ValueError(f"{name} must be a contiguous float32 [B] tensor")
+        _vec(w, B, "w", dev)
+        if self.selection:
+            if bsdf_pdf is None:
+                raise ValueError("a selection network trains on the blended loss: bsdf_pdf is required")
+            _vec(bsdf_pdf, B, "bsdf_pdf", dev)
+        elif bsdf_pdf is not None:
+            raise ValueError("bsdf_pdf needs a network with the selection output")
         return B, ld
 
     def loss_grad(self, feat, dirs, w, bsdf_pdf=None):
@@ -220,21 +309,25 @@ def blend_ramp(frames_done, M=4, B=64):
 
 
 class NasgNLL(torch.autograd.Function):
-    """Weighted NLL of Sec. 4.2 with the library's fused backward.
+    """Weighted NLL of Sec. 4.2 (or, for a selection network, the blended
+    loss) with the library's fused backward.
 
-    loss = NasgNLL.apply(guide.w, guide, feat, dirs, w). The forward runs the
-    fused kernel once (loss and weight gradient together, activations
-    recomputed on chip and never stored); backward scales that gradient.
+    loss = NasgNLL.apply(guide.w, guide, feat, dirs, w[, bsdf_pdf]). The
+    forward re-packs guide.w into the kernels' layout (a torch optimiser may
+    have changed it in place since the last call), then runs the fused kernel
+    once: loss and weight gradient together, activations recomputed on chip
+    and never stored. backward scales that gradient by the upstream one.
     """
 
     @staticmethod
-    def forward(ctx, weights, guide, feat, dirs, w):
+    def forward(ctx, weights, guide, feat, dirs, w, bsdf_pdf=None):
         if weights.data_ptr() != guide.w.data_ptr():
             raise ValueError("weights must be guide.w")
-        guide.loss_grad(feat, dirs, w)
+        guide.repack()
+        guide.loss_grad(feat, dirs, w, bsdf_pdf)
         ctx.grad = guide.grad.clone()
         return guide.stats[0].to(torch.float32)
 
     @staticmethod
     def backward(ctx, gout):
-        return gout * ctx.grad, None, None, None, None
+        return gout * ctx.grad, None, None, None, None, None

@@ -1,0 +1,168 @@
+"""Seeded inputs at the edges of the NASG method (test plumbing).
+
+Records with extreme sharpness and eccentricity (lambda from 1e-3 to e^15,
+a from 0 to e^15, the clamp bounds), directions within 1e-7 .. 1e-1 rad of
+a lobe's +z and -z (toward x, toward y and in between) and on its y
+meridian, extreme uniforms for the sampler, and networks whose output layer
+is scaled row by row so that raw outputs reach |o| ~ 40 (past the clamp at
+15 and the series/exp switch of the decode at 1/8, with (cos, sin) pairs that
+are exactly zero).
+
+Only geometry and parameter grids are built here; the one NASG quantity a
+record needs, log(A_k / K_k), comes from the oracle's closed-form normaliser
+(eq. "K for NASG"), never from the HIP path.
+"""
+
+import math
+
+import numpy as np
+import torch
+
+from oracle import nasg as onasg
+from paper_2303_08064_amd import synth
+
+LAMBDAS = (1e-3, 0.1, 1.0, 10.0, 1e2, 1e3, 1e4, math.exp(15.0))
+ECCS = (0.0, 1e-3, 1.0, 1e2, 1e3, math.exp(15.0))
+ANGLES = (0.0, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)
+U1 = float(np.float32(1.0 - 2.0 ** -24))     # the largest float32 below one
+XI0 = (0.0, 1e-3, 0.5, 0.999, U1)
+XI1 = (0.0, 0.25, 0.5, U1)
+XI2 = (0.5, 0.75)                           # 1/2 exactly: the western map
+
+
+def random_frames(n, rng):
+    """(z, x) [n, 3] float64: orthonormal lobe frames, uniformly oriented."""
+    z = synth.unit_vectors(n, rng)
+    t = rng.standard_normal((n, 3))
+    t -= (t * z).sum(1, keepdims=True) * z
+    x = t / np.linalg.norm(t, axis=1, keepdims=True)
+    return z, x
+
+
+def records(lam0, a0, K, rng, eps=0.0, dominant=True):
+    """[n, K, 9] float32 records; lobe 0 of vertex i has sharpness lam0[i] and
+    eccentricity a0[i]; the other lobes are moderate (lambda in [1, 50],
+    a in [0, 5]). dominant: lobe 0 carries all but 1e-6 per other lobe of the
+    mixture weight; else half of it."""
+    n = len(lam0)
+    z, x = random_frames(n * K, rng)
+    lam = np.exp(rng.uniform(0.0, math.log(50.0), (n, K)))
+    a = rng.uniform(0.0, 5.0, (n, K))
+    lam[:, 0], a[:, 0] = lam0, a0
+    if dominant:
+        A = np.full((n, K), 1e-6)
+        A[:, 0] = 1.0 - 1e-6 * (K - 1)
+    else:
+        A = rng.uniform(0.5, 1.5, (n, K))
+        A[:, 1:] *= 1.0 / A[:, 1:].sum(1, keepdims=True)
+        A[:, 0] = A[:, 1:].sum(1)
+        A /= A.sum(1, keepdims=True)
+    # the record stores float32 values: lambda and a are rounded first, and
+    # log K is taken of the rounded values
+    lam32 = lam.astype(np.float32).astype(np.float64)
+    a32 = a.astype(np.float32).astype(np.float64)
+    logK = onasg.log_normaliser(torch.tensor(lam32), torch.tensor(a32), eps).numpy()
+    rec = np.concatenate([z.reshape(n, K, 3), x.reshape(n, K, 3), lam32[..., None], a32[..., None],
+                          (np.log(A) - logK)[..., None]], axis=-1)
+    return rec.astype(np.float32)
+
+
+def near_axis_dirs(z, x, sign, angle, psi):
+    """Unit directions at `angle` rad from sign * z, in the azimuth psi
+    measured from x (psi = pi/2: toward y = z x x). Arrays [n, 3] / [n]."""
+    y = np.cross(z, x)
+    t = np.cos(psi)[:, None] * x + np.sin(psi)[:, None] * y
+    return np.cos(angle)[:, None] * sign * z + np.sin(angle)[:, None] * t
+
+
+def meridian_dirs(z, x, t):
+    """v = cos t z + sin t y on the lobe's y meridian (t in [0, pi])."""
+    y = np.cross(z, x)
+    return np.cos(t)[:, None] * z + np.sin(t)[:, None] * y
+
+
+def record_grid(K, eps, seed):
+    """Records and directions over the (lambda, a) grid: for every cell, one
+    vertex per direction in {near +z, near -z} x ANGLES x azimuth
+    {0, pi/4, pi/2, random}, the y meridian at t in {pi/2, 3pi/4, pi - 1e-2,
+    pi - 1e-4}, and 8 uniform directions. Lobe 0 is the cell's lobe and
+    dominates the mixture in half of the vertices.
+    Returns (rec [n, K, 9] float32, dirs [n, 3] float32, cell [n, 2] int)."""
+    rng = synth.rng_for(seed)
+    per_lobe = []
+    for sign in (1.0, -1.0):
+        for ang in ANGLES:
+            for psi in (0.0, math.pi / 4, math.pi / 2, None):
+                per_lobe.append(("axis", sign, ang, psi))
+    for t in (math.pi / 2, 3 * math.pi / 4, math.pi - 1e-2, math.pi - 1e-4):
+        per_lobe.append(("meridian", t))
+    per_lobe += [("uniform",)] * 8
+    m = len(per_lobe)
+    lam0, a0, cell = [], [], []
+    for i, lam in enumerate(LAMBDAS):
+        for j, a in enumerate(ECCS):
+            lam0 += [lam] * m
+            a0 += [a] * m
+            cell += [(i, j)] * m
+    n = len(lam0)
+    dom = np.arange(n) % 2 == 0
+    rec = np.empty((n, K, 9), np.float32)
+    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True)
+    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False)
+    z = rec[:, 0, 0:3].astype(np.float64)
+    x = rec[:, 0, 3:6].astype(np.float64)
+    dirs = np.empty((n, 3))
+    for r in range(n):
+        kind = per_lobe[r % m]
+        zr, xr = z[r:r + 1], x[r:r + 1]
+        if kind[0] == "axis":
+            _, sign, ang, psi = kind
+            psi = rng.uniform(0, 2 * math.pi) if psi is None else psi
+            dirs[r] = near_axis_dirs(zr, xr, sign, np.array([ang]), np.array([psi]))[0]
+        elif kind[0] == "meridian":
+            dirs[r] = meridian_dirs(zr, xr, np.array([kind[1]]))[0]
+        else:
+            dirs[r] = synth.unit_vectors(1, rng)[0]
+    return rec, dirs.astype(np.float32), np.array(cell)
+
+
+def sample_grid(K, eps, seed):
+    """Records over the (lambda, a) grid with every combination of the
+    extreme uniforms: xi_sel in {0, 1/4, U1} (lobe 0 is chosen by 0 and, when
+    it dominates, by 1/4; U1 picks the last lobe), xi0 in XI0, xi1 in XI1,
+    xi2 in XI2. Returns (rec [n, K, 9], xi [n, 4] float32, cell [n, 2])."""
+    rng = synth.rng_for(seed)
+    combos = [(s, a, b, c) for s in (0.0, 0.25, U1) for a in XI0 for b in XI1 for c in XI2]
+    m = len(combos)
+    lam0, a0, cell, xi = [], [], [], []
+    for i, lam in enumerate(LAMBDAS):
+        for j, a in enumerate(ECCS):
+            lam0 += [lam] * m
+            a0 += [a] * m
+            cell += [(i, j)] * m
+            xi += combos
+    n = len(lam0)
+    dom = np.arange(n) % 2 == 0
+    rec = np.empty((n, K, 9), np.float32)
+    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True)
+    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False)
+    return rec, np.array(xi, dtype=np.float32), np.array(cell)
+
+
+def scaled_output_weights(mats, seed, max_scale=1000.0, zero_pairs=True):
+    """Scale the output layer row by row by log-uniform factors in
+    [1, max_scale] so that raw outputs span |o| from ~0 to ~40 (at the
+    default initialisation, |o| per unit scale is ~0.05); with zero_pairs the
+    (sin phi, cos phi) rows of lobe 0 and the (sin tau, cos tau) rows of lobe 1
+    are zeroed, so those pairs are exactly (0, 0)."""
+    rng = synth.rng_for(seed)
+    out = [m.copy() for m in mats]
+    W = out[-1].astype(np.float64)
+    f = np.exp(rng.uniform(0.0, math.log(max_scale), W.shape[0]))
+    W *= f[:, None]
+    if zero_pairs:
+        K = W.shape[0] // 8
+        for p, k in ((1, 0), (2, 0), (3, 1), (4, 1)):
+            W[p * K + k] = 0.0
+    out[-1] = W.astype(np.float32)
+    return out

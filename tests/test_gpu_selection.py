@@ -164,14 +164,28 @@ def test_selection_training_is_deterministic():
 
 
 def test_selection_argument_checks():
-    from paper_2303_08064_amd._lib import NasgError
+    """The binding refuses a selection network's loss without p_fs, p_fs for a
+    network without the selection output, and sel_out there, before any
+    launch; the C ABI refuses the same calls with NASG_E_ARG."""
+    import ctypes
+    from paper_2303_08064_amd._lib import NASG_E_ARG
     g, _ = make_guide("c2s_f32")
     feat, dirs, w, pdf = _batch(256, 48)
-    with pytest.raises(NasgError, match="bsdf_pdf"):
-        g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
+    f, d, wt, p = to_dev(feat), to_dev(dirs), to_dev(w), to_dev(pdf)
+    with pytest.raises(ValueError, match="bsdf_pdf"):
+        g.loss_grad(f, d, wt)
     g2, _ = make_guide("c2_f32")
-    with pytest.raises(NasgError, match="bsdf_pdf"):
-        g2.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
-    xi = synth.uniforms(256, synth.rng_for(49))
-    with pytest.raises(NasgError, match="sel_out"):
-        g2.query(to_dev(feat), to_dev(xi), sel_out=torch.empty(256, device="cuda"))
+    with pytest.raises(ValueError, match="bsdf_pdf"):
+        g2.loss_grad(f, d, wt, bsdf_pdf=p)
+    xi = to_dev(synth.uniforms(256, synth.rng_for(49)))
+    with pytest.raises(ValueError, match="sel_out"):
+        g2.query(f, xi, sel_out=torch.empty(256, device="cuda"))
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert g.lib.nasg_loss_grad(g._ctx, P(f), P(d), P(wt), None, 256, 256, st) == NASG_E_ARG
+    assert b"bsdf_pdf" in g.lib.nasg_last_error()
+    assert g2.lib.nasg_loss_grad(g2._ctx, P(f), P(d), P(wt), P(p), 256, 256, st) == NASG_E_ARG
+    dout, pout, sel = (torch.empty(3, 256, device="cuda"), torch.empty(256, device="cuda"),
+                       torch.empty(256, device="cuda"))
+    assert g2.lib.nasg_query(g2._ctx, P(f), P(xi), 256, 256, P(dout), P(pout), P(sel), None, st) == NASG_E_ARG
+    assert b"sel_out" in g2.lib.nasg_last_error()

@@ -323,6 +323,88 @@ def test_sample_value_matches_sampling_variables():
     assert np.max(np.abs(lg - pred)) < 1e-9
 
 
+def test_record_path_equals_decode_path():
+    """The record of a decoded mixture (z, x, lambda, a, log(A_k/K_k)) carries
+    the whole mixture: rebuilt from the record, the mixture pdf, its
+    direction gradient and the sampler (which recovers A_k through the
+    closed-form K, eq. "K for NASG") give what the decoded lobes give, in
+    float64, for epsilon 0 and 0.3 and lambda, a spanning the clamp range."""
+    rng = np.random.default_rng(31)
+    K, B = 6, 300
+    raw = rng.standard_normal((B, 8 * K)) * 2.0
+    raw[:, 5 * K:7 * K] = rng.uniform(-15, 15, (B, 2 * K))
+    v = rng.standard_normal((B, 3)); v /= np.linalg.norm(v, axis=1, keepdims=True)
+    xi = rng.random((B, 4))
+    for eps in (0.0, 0.3):
+        lob = nasg.decode(torch.tensor(raw), K, eps)
+        rl = nasg.lobes_from_record(lob.record(), eps)
+        a = nasg.mixture_log_pdf(torch.tensor(v), lob).numpy()
+        b = nasg.mixture_log_pdf(torch.tensor(v), rl).numpy()
+        fin = np.isfinite(a)
+        assert np.array_equal(fin, np.isfinite(b))
+        assert np.max(np.abs(a[fin] - b[fin]) / np.maximum(1.0, np.abs(a[fin]))) < 1e-12
+        ga = nasg.log_pdf_direction_grad(torch.tensor(v), lob).numpy()
+        gb = nasg.log_pdf_direction_grad(torch.tensor(v), rl).numpy()
+        ok = np.isfinite(ga).all(1)
+        assert np.allclose(ga[ok], gb[ok], rtol=1e-9, atol=1e-9)
+        va, ka = nasg.sample(lob, torch.tensor(xi))
+        vb, kb = nasg.sample_from_record(lob.record(), torch.tensor(xi), eps)
+        assert torch.equal(ka, kb)
+        assert float(torch.abs(va - vb).max()) < 1e-9
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.3])
+def test_mixture_sampler_chi_square_against_pdf(eps):
+    """The mixture sampler (inverse-CDF lobe choice composed with the App. C
+    lobe sampler) draws from the mixture density D = sum_k A_k G_k / K_k
+    (Sec. 3.1): chi-square of a histogram in global (cos theta, phi) bins
+    against the quadrature of D over each bin. A lobe index off by one, a
+    weight taken without normalisation, or a lobe sampled in another lobe's
+    frame moves probability between bins far beyond the test's power."""
+    rng = np.random.default_rng(32)
+    K, n = 4, 400_000
+    raw = rng.standard_normal((1, 8 * K))
+    raw[0, 5 * K:6 * K] = np.log([3.0, 12.0, 1.0, 30.0])
+    raw[0, 6 * K:7 * K] = np.log([0.5, 20.0, 2.0, 100.0])
+    raw[0, 7 * K:8 * K] = [0.3, -0.4, 0.8, -1.2]
+    one = nasg.decode(torch.tensor(raw), K, eps)
+    rep = lambda t: t.expand(n, *t.shape[1:])
+    lob = nasg.Lobes(z=rep(one.z), x=rep(one.x), y=rep(one.y), lam=rep(one.lam), a=rep(one.a),
+                     log_A=rep(one.log_A), log_K=rep(one.log_K), eps=eps)
+    v, k = nasg.sample(lob, torch.tensor(rng.random((n, 4))))
+    v = v.numpy()
+    # the lobe choice alone follows A
+    freq = np.bincount(k.numpy(), minlength=K) / n
+    A = torch.exp(one.log_A[0]).numpy()
+    assert np.max(np.abs(freq - A) / np.sqrt(A * (1 - A) / n)) < 5
+    mu_e = np.linspace(-1, 1, 13)
+    ph_e = np.linspace(-math.pi, math.pi, 17)
+    counts, _, _ = np.histogram2d(np.clip(v[:, 2], -1, 1), np.arctan2(v[:, 1], v[:, 0]), bins=[mu_e, ph_e])
+    prob = np.zeros_like(counts)
+    ez, ex, ey = np.array([0.0, 0, 1]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    for i in range(len(mu_e) - 1):
+        mb = np.linspace(mu_e[i], mu_e[i + 1], 17)
+        for j in range(len(ph_e) - 1):
+            pb = np.linspace(ph_e[j], ph_e[j + 1], 17)
+            vv, ww = quad.sphere_nodes(ez, ex, ey, mb, pb, 12)
+            m = vv.reshape(-1, 3).shape[0]
+            lq = nasg.mixture_log_pdf(torch.tensor(vv.reshape(-1, 3)), nasg.Lobes(
+                z=one.z.expand(m, K, 3), x=one.x.expand(m, K, 3), y=one.y.expand(m, K, 3),
+                lam=one.lam.expand(m, K), a=one.a.expand(m, K), log_A=one.log_A.expand(m, K),
+                log_K=one.log_K.expand(m, K), eps=eps)).numpy()
+            prob[i, j] = (np.exp(lq).reshape(ww.shape) * ww).sum()
+    assert abs(prob.sum() - 1) < 1e-4
+    exp_c, obs = prob.ravel() * n, counts.ravel()
+    keep = exp_c >= 5
+    chi2 = (((obs[keep] - exp_c[keep]) ** 2) / exp_c[keep]).sum()
+    rest_e, rest_o = exp_c[~keep].sum(), obs[~keep].sum()
+    dof = int(keep.sum()) - 1
+    if rest_e >= 5:
+        chi2 += (rest_o - rest_e) ** 2 / rest_e
+        dof += 1
+    assert ss.chi2.sf(chi2, dof) > 1e-4, (chi2, dof)
+
+
 def test_choose_lobe_inverse_cdf():
     log_A = torch.log(torch.tensor([[0.1, 0.2, 0.3, 0.4]] * 5, dtype=F64))
     xi = torch.tensor([0.0, 0.15, 0.2999, 0.61, 0.99999], dtype=F64)
@@ -359,6 +441,45 @@ def test_mlp_is_plain_matmul_chain():
     refb = h @ Wb[-1].T
     gotb = mlp.forward([torch.tensor(W) for W in Ws], torch.tensor(feat), bf16=True).numpy()
     assert np.allclose(gotb, refb, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_backward_is_the_rounded_chain_rule():
+    """The BF16 emulation's backward: the chain rule written out in NumPy with
+    integer round-to-nearest-even, the deltas rounded to float32 then bfloat16
+    at every layer (the raw-output gradient included), products and sums in
+    float64. A delta left unrounded at any one layer moves that layer's
+    gradient by ~2^-9 relative and fails the 1e-12 bound."""
+    rng = np.random.default_rng(19)
+    shapes = mlp.layer_shapes(16, 3, 2)
+    Ws = [rng.standard_normal(s) * 0.4 for s in shapes]
+    B = 40
+    feat = rng.standard_normal((B, 9))
+    g_raw = rng.standard_normal((B, shapes[-1][0])) * 1e-2
+    Wb = [_np_bf16(W) for W in Ws]
+    hs, ys = [_np_bf16(np.concatenate([feat, np.ones((B, 1))], 1))], []
+    for W in Wb[:-1]:
+        y = (hs[-1] @ W.T).astype(np.float32).astype(np.float64)
+        ys.append(y)
+        hs.append(_np_bf16(np.maximum(y, 0)))
+    d = _np_bf16(g_raw)
+    ref = [None] * len(Ws)
+    for l in range(len(Ws) - 1, -1, -1):
+        ref[l] = d.T @ hs[l]
+        if l > 0:
+            d = _np_bf16((d @ Wb[l]) * (ys[l - 1] > 0))
+    got = train.weight_grad_from_raw_grad([torch.tensor(W) for W in Ws], torch.tensor(feat),
+                                          torch.tensor(g_raw), bf16=True)
+    for a, b in zip(got, ref):
+        assert np.allclose(a.numpy(), b, rtol=1e-12, atol=1e-15)
+    # and without rounding the deltas the result differs at every layer
+    plain = [None] * len(Ws)
+    d = g_raw
+    for l in range(len(Ws) - 1, -1, -1):
+        plain[l] = d.T @ hs[l]
+        if l > 0:
+            d = (d @ Wb[l]) * (ys[l - 1] > 0)
+    for a, b in zip(got, plain):
+        assert np.abs(a.numpy() - b).max() > 1e-6 * np.abs(b).max()
 
 
 def test_log_normaliser_derivatives():
