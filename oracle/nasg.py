@@ -54,6 +54,26 @@ def _unit_pair(c, s):
     return c1 / n, s1 / n
 
 
+class _SinFromCos(torch.autograd.Function):
+    """sin = sqrt(max(0, 1 - cos^2)) with its derivative -cos / sin, taken as
+    0 where 1 - cos^2 rounds to 0 in float64 (|raw| above ~37: the exact
+    derivative, -cos sin / 2 per unit of the raw output, is below 1e-8
+    there, while the literal chain rule would give infinity times a
+    vanishing factor)."""
+
+    @staticmethod
+    def forward(ctx, c):
+        s = torch.sqrt(torch.clamp(1.0 - c * c, min=0.0))
+        ctx.save_for_backward(c, s)
+        return s
+
+    @staticmethod
+    def backward(ctx, g):
+        c, s = ctx.saved_tensors
+        safe = torch.where(s > 0, s, torch.ones_like(s))
+        return torch.where(s > 0, -g * c / safe, torch.zeros_like(g))
+
+
 def log_normaliser(lam, a, eps=0.0):
     """log K, with K = 2 pi (1 - e^{-2 lam}) / (lam sqrt((1+eps)(1+eps+a))).
 
@@ -91,7 +111,7 @@ def decode(raw, n_lobes, eps=0.0, isotropic=False):
     r = raw[:, :N_PARAM * n_lobes].reshape(raw.shape[0], N_PARAM, n_lobes)
     d = torch.sigmoid(r[:, 0:5, :]) * 2.0 - 1.0
     ct = d[:, 0]
-    st = torch.sqrt(torch.clamp(1.0 - ct * ct, min=0.0))
+    st = _SinFromCos.apply(ct)
     cp, sp = _unit_pair(d[:, 2], d[:, 1])
     ctau, stau = _unit_pair(d[:, 4], d[:, 3])
     z, x, y = euler_frame(ct, st, cp, sp, ctau, stau)

@@ -767,3 +767,27 @@ def test_isotropic_decode_is_vmf_mixture():
         ref[b] = np.log(sum(A[b, k] * np.exp(ss.vonmises_fisher(mu=lob.z[b, k].numpy(), kappa=float(lob.lam[b, k])).logpdf(d[b]))
                             for k in range(K)))
     assert np.abs(lq - ref).max() < 1e-9
+
+
+def test_sin_theta_derivative_at_saturation():
+    """sin theta = sqrt(1 - cos^2 theta) of the decode: where float64 rounds
+    1 - cos^2 to zero (|raw| above ~37) its derivative is taken as zero (the
+    exact one, -cos sin / 2 per unit of the raw output, is below 1e-8);
+    elsewhere it is the plain chain rule, checked against central
+    differences."""
+    K = 1
+    raw = torch.zeros(4, 8, dtype=F64)
+    raw[:, 0] = torch.tensor([40.0, -45.0, 0.7, -2.0])
+    raw[:, 1:5] = 0.3
+    raw.requires_grad_(True)
+    z = nasg.decode(raw, K).z
+    (g,) = torch.autograd.grad(z[..., 0].sum() + z[..., 1].sum(), raw)
+    assert torch.isfinite(g).all()
+    assert float(g[0, 0]) == 0.0 and float(g[1, 0]) == 0.0
+    h = 1e-6
+    for i in (2, 3):
+        rp, rm = raw.detach().clone(), raw.detach().clone()
+        rp[i, 0] += h
+        rm[i, 0] -= h
+        fd = ((nasg.decode(rp, K).z[i, 0, :2].sum() - nasg.decode(rm, K).z[i, 0, :2].sum()) / (2 * h))
+        assert abs(float(g[i, 0]) - float(fd)) < 1e-8
