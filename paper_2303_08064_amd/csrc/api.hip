@@ -338,9 +338,10 @@ static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
-nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
-                           const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
-  static const char* fn = "nasg_loss_grad";
+// the loss and gradient launches of nasg_loss_grad and nasg_train_step; fn
+// names the entry point in error messages
+static nasg_status loss_grad(nasg_ctx* ctx, const char* fn, const float* feat, const float* dir, const float* w,
+                             const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
   NASG_TRY(check_batch(fn, ld, B));
   if (B > ctx->cfg.max_batch) return fail(NASG_E_SHAPE, fn, "B > max_batch");
@@ -413,6 +414,11 @@ nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, c
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
+nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
+                           const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
+  return loss_grad(ctx, "nasg_loss_grad", feat, dir, w, bsdf_pdf, ld, B, stream);
+}
+
 nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_adam_step", "ctx is NULL");
   return adam_only(ctx, "nasg_adam_step", stream);
@@ -420,7 +426,7 @@ nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream) {
 
 nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
                             const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
-  NASG_TRY(nasg_loss_grad(ctx, feat, dir, w, bsdf_pdf, ld, B, stream));
+  NASG_TRY(loss_grad(ctx, "nasg_train_step", feat, dir, w, bsdf_pdf, ld, B, stream));
   return adam_only(ctx, "nasg_train_step", stream);
 }
 

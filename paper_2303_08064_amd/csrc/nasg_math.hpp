@@ -20,6 +20,10 @@ constexpr float kLog2e = 1.44269504088896341f;
 constexpr float kLn2 = 0.693147180559945309f;
 constexpr float kLog2Pi = 1.83787706640934548f;   // log(2 pi)
 constexpr float kLogClamp = 15.0f;                // log lambda, log a in [-15, 15]
+// X^2 + Y^2 below the normal float range (v within ~1e-19 rad of the lobe
+// axis): 1/(X^2 + Y^2) would overflow, so the anisotropy weight c^2 and its
+// derivatives are taken as 0 there
+constexpr float kMinNormal = 1.17549435e-38f;
 
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
@@ -202,8 +206,11 @@ struct Eval {
   float ell;      // log c + log G(v)
   float L;        // log u
   float u;        // (v.z + 1)/2
-  float E;        // expm1(p L) = u^p - 1
-  float p, c2;    // exponent and anisotropy weight
+  float w;        // 1 - u = |v - z|^2 / 4
+  float E;        // expm1(p L) = u^p - 1 (accurate near u^p = 1)
+  float epl;      // u^p = e^{p L} (accurate where it is tiny)
+  float p, pm1;   // exponent p = 1 + eps + a c^2 and p - 1 = eps + a c^2
+  float c2;       // anisotropy weight
   float X, Y, S;  // v.x, v.y, X^2 + Y^2
   float invS;     // 1 / S (used again by the derivatives)
 };
@@ -230,14 +237,20 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
   r.L = fsel(w < 0.0625f, lw, lu);
   r.u = u;
+  r.w = w;
   r.X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
   r.Y = fmaf(vx, yx, fmaf(vy, yy, vz * yz));
   r.S = fmaf(r.X, r.X, r.Y * r.Y);
   r.invS = frcp(r.S);
-  r.c2 = fsel(r.S > 0.0f, r.X * r.X * r.invS, 0.0f);
-  r.p = 1.0f + eps + L.a * r.c2;
-  r.E = expm1f_(r.p * r.L);
-  float lg = fmaf(2.0f * L.lam, r.E, (r.p - 1.0f) * r.L);
+  r.c2 = fsel(r.S >= kMinNormal, r.X * r.X * r.invS, 0.0f);
+  r.pm1 = fmaf(L.a, r.c2, eps);
+  r.p = 1.0f + r.pm1;
+  const float pl = r.p * r.L;
+  r.E = expm1f_(pl);
+  // u^p from the exponential expm1 already evaluates for |p L| >= 1/8: E + 1
+  // would round a tiny u^p to 0
+  r.epl = fsel(fabsf(pl) < 0.125f, r.E + 1.0f, fexp(pl));
+  float lg = fmaf(2.0f * L.lam, r.E, r.pm1 * r.L);
   // G(-z) = 0: u == 0 only when v = -z exactly
   r.ell = fsel(u > 0.0f, L.logc + lg, -INFINITY);
   return r;
@@ -259,49 +272,75 @@ __device__ __forceinline__ float eval_lobe_ell(const Lobe& L, float vx, float vy
   const float Lu = fsel(w < 0.0625f, lw, lu);
   const float X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
   const float S = w4 * u;
-  const float c2 = fsel(S > 0.0f, fminf(X * X * frcp(S), 1.0f), 0.0f);
-  const float p = 1.0f + eps + L.a * c2;
-  const float lg = fmaf(2.0f * L.lam, expm1f_(p * Lu), (p - 1.0f) * Lu);
+  const float c2 = fsel(S >= kMinNormal, fminf(X * X * frcp(S), 1.0f), 0.0f);
+  const float pm1 = fmaf(L.a, c2, eps);                    // p - 1 without cancellation
+  const float lg = fmaf(2.0f * L.lam, expm1f_((1.0f + pm1) * Lu), pm1 * Lu);
   return fsel(u > 0.0f, L.logc + lg, -INFINITY);
 }
 
-// Euclidean gradient with respect to v of ell = log c + log G (eq. NASG; App.
-// A) at a unit v, through v.z, X = v.x and Y = v.y (the same partials as
-// backward_lobe): d ell/d(v.z) = (2 lam p u^p + p - 1) / (2u) and, with
-// d ell/dp = log u (2 lam u^p + 1), the anisotropy c^2 = X^2 / (X^2 + Y^2)
-// contributes a d ell/dp (2 X Y^2, -2 Y X^2) / (X^2 + Y^2)^2. Zero where the
-// lobe vanishes (v = -z). Callers project onto the tangent plane of the
-// sphere, where any extension of the lobe off the sphere has this gradient.
-__device__ __forceinline__ void dir_grad_lobe(const Lobe& L, const Eval& e, float& gx, float& gy, float& gz) {
+// Gradient on the sphere of ell = log c + log G (eq. NASG; App. A) at a unit
+// v, through v.z, X = v.x and Y = v.y (the same partials as backward_lobe):
+// d ell/d(v.z) = (2 lam p u^p + p - 1) / (2u) and, with d ell/dp =
+// log u (2 lam u^p + 1), the anisotropy c^2 = X^2 / (X^2 + Y^2) contributes
+// a d ell/dp (2 X Y^2, -2 Y X^2) / (X^2 + Y^2)^2. Each partial multiplies the
+// tangential part a - (v.a) v of its axis a, so the sum is tangential as it
+// stands. Near the axis z - (v.z) v is formed without cancellation: as
+// (v + z) - 2u v in the lobe's southern hemisphere and (z - v) + 2(1 - u) v
+// in the northern one (exact identities, since 1 + v.z = 2u and 1 - v.z =
+// 2(1 - u)); X/S and Y/S are formed before the products, so nothing
+// overflows when v is within ~1e-10 rad of the axis. Zero where the lobe
+// vanishes (v = -z).
+__device__ __forceinline__ void dir_grad_lobe(const Lobe& L, const Eval& e, float vx, float vy, float vz,
+                                              float& gx, float& gy, float& gz) {
   const bool live = e.u > 0.0f;
-  const float epl = e.E + 1.0f;   // u^p
+  const float epl = e.epl;   // u^p
   const float twolam = 2.0f * L.lam;
-  const float GZ = fsel(live, fmaf(twolam * e.p, epl, e.p - 1.0f) * frcp(2.0f * e.u), 0.0f);
+  const float GZ = fsel(live, fmaf(twolam * e.p, epl, e.pm1) * frcp(2.0f * e.u), 0.0f);
   const float Dp = e.L * fmaf(twolam, epl, 1.0f);
-  const float coef = fsel(live && e.S > 0.0f, L.a * Dp * 2.0f * e.invS * e.invS, 0.0f);
-  const float GX = coef * e.X * e.Y * e.Y;
-  const float GY = -coef * e.Y * e.X * e.X;
+  const float coef = fsel(live && e.S >= kMinNormal, 2.0f * L.a * Dp, 0.0f);
+  const float xs = e.X * e.invS, ys = e.Y * e.invS;
+  const float GX = coef * xs * (e.Y * ys);
+  const float GY = -coef * ys * (e.X * xs);
   float yx, yy, yz;
   cross(L.zx, L.zy, L.zz, L.xx, L.xy, L.xz, yx, yy, yz);
-  gx = fmaf(GZ, L.zx, fmaf(GX, L.xx, GY * yx));
-  gy = fmaf(GZ, L.zy, fmaf(GX, L.xy, GY * yy));
-  gz = fmaf(GZ, L.zz, fmaf(GX, L.xz, GY * yz));
+  const bool south = e.u <= 0.5f;
+  const float sg = fsel(south, 1.0f, -1.0f);
+  const float f = fsel(south, -2.0f * e.u, 2.0f * e.w);
+  const float tzx = fmaf(f, vx, fmaf(sg, vx, L.zx));
+  const float tzy = fmaf(f, vy, fmaf(sg, vy, L.zy));
+  const float tzz = fmaf(f, vz, fmaf(sg, vz, L.zz));
+  gx = fmaf(GZ, tzx, fmaf(GX, fmaf(-e.X, vx, L.xx), GY * fmaf(-e.Y, vx, yx)));
+  gy = fmaf(GZ, tzy, fmaf(GX, fmaf(-e.X, vy, L.xy), GY * fmaf(-e.Y, vy, yy)));
+  gz = fmaf(GZ, tzz, fmaf(GX, fmaf(-e.X, vz, L.xz), GY * fmaf(-e.Y, vz, yz)));
 }
 
 // One direction from a single lobe (App. C): (xi0, xi1) -> (s, rho) linearly,
-// xi2 > 1/2 east. Stable form: log s = log(1 + (1 - xi0)(e^{-2 lam} - 1)),
-// (cos theta + 1)/2 = (1 + log s / (2 lam))^{1/p} with p = 1 + eps + a cos^2 phi,
-// and (cos phi, sin phi) proportional to (cos rho, sqrt((1+eps+a)/(1+eps)) sin rho).
+// xi2 > 1/2 east. Stable form: (cos theta + 1)/2 = u with log u = log(1 + r)/p,
+// r = log s / (2 lam) in [-1, 0], p = 1 + eps + a cos^2 phi, and (cos phi,
+// sin phi) proportional to (cos rho, sqrt((1+eps+a)/(1+eps)) sin rho).
+// log(1 + r) is taken two ways, each where it has no cancellation:
+//  * r > -1/2: log1p(r), with log s = log(1 + (1 - xi0)(e^{-2 lam} - 1)) by
+//    log1p (s > 1/2) or as the log of s itself;
+//  * r <= -1/2 (s near its least value e^{-2 lam}, the lobe's far side):
+//    1 + r = log(s e^{2 lam}) / (2 lam) = log1p(xi0 expm1(2 lam)) / (2 lam),
+//    so xi0 = 0 gives exactly v = -z; beyond 2 lam = 88, where e^{-2 lam} is
+//    below the normal float range, s = xi0 (to 1e-8 relative for xi0 >=
+//    1e-30) and 1 + r = 1 + log(xi0) / (2 lam), 0 for xi0 = 0.
 __device__ __forceinline__ void sample_lobe(const Lobe& L, float xi0, float xi1, float xi2,
                                             float eps, float& vx, float& vy, float& vz) {
-  float t = expm1f_(-2.0f * L.lam);                  // e^{-2 lam} - 1 in (-1, 0)
-  float y0 = (1.0f - xi0) * t;
+  const float tl = 2.0f * L.lam;
+  const float rtl = frcp(tl);
+  float t = expm1f_(-tl);                              // e^{-2 lam} - 1 in (-1, 0)
+  float y0 = (1.0f - xi0) * t;                         // s - 1
   float ls_near = log1pf_(y0);
-  float ls_far = flog(fmaf(1.0f - xi0, fexp(-2.0f * L.lam), xi0));
+  float ls_far = flog(fmaf(1.0f - xi0, fexp(-tl), xi0));
   float ls = fsel(y0 > -0.5f, ls_near, ls_far);
-  ls = fmaxf(ls, -2.0f * L.lam);                       // s >= e^{-2 lam}
-  float rr = ls * frcp(2.0f * L.lam);                  // in [-1, 0]
-  rr = fmaxf(rr, -1.0f);
+  ls = fmaxf(ls, -tl);                                 // s >= e^{-2 lam}
+  float rr = fmaxf(ls * rtl, -1.0f);                   // in [-1, 0]
+  float opr_small = log1pf_(xi0 * expm1f_(fminf(tl, 88.0f))) * rtl;
+  float opr_big = fsel(xi0 > 0.0f, fmaf(ls, rtl, 1.0f), 0.0f);
+  float opr = fsel(tl <= 88.0f, opr_small, opr_big);  // 1 + r near 0
+  float lopr = fsel(rr > -0.5f, log1pf_(rr), flog(opr));
   // cos(rho) = sin(pi xi1), sin(rho) = -cos(pi xi1); v_sin/v_cos take revolutions
   float crho = __builtin_amdgcn_sinf(0.5f * xi1);
   float srho = -__builtin_amdgcn_cosf(0.5f * xi1);
@@ -310,7 +349,7 @@ __device__ __forceinline__ void sample_lobe(const Lobe& L, float xi0, float xi1,
   unit_pair(crho, k * srho, cphi, sphi, inv);
   if (!(xi2 > 0.5f)) { cphi = -cphi; sphi = -sphi; }
   float p = fmaf(L.a, cphi * cphi, 1.0f + eps);
-  float Lu = log1pf_(rr) * frcp(p);                    // log((cos theta + 1)/2)
+  float Lu = lopr * frcp(p);                           // log((cos theta + 1)/2)
   float u = fexp(Lu);
   float om = -expm1f_(Lu);                             // 1 - u
   float ct = 1.0f - 2.0f * om;
@@ -338,7 +377,7 @@ __device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, c
                                               float vx, float vy, float vz, float eps,
                                               float gk, float galpha, float g[8]) {
   bool live = e.u > 0.0f && gk != 0.0f;
-  float epl = e.E + 1.0f;
+  float epl = e.epl;
   float twolam = 2.0f * L.lam;
   // log lambda
   g[5] = fsel(A.lam_in && live, gk * (twolam * e.E - A.qlam + 1.0f), 0.0f);
@@ -348,11 +387,13 @@ __device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, c
   g[6] = fsel(A.a_in && live, gk * ga, 0.0f);
   g[7] = galpha;
   // direction terms
-  float DL = fmaf(twolam * e.p, epl, e.p - 1.0f);
+  float DL = fmaf(twolam * e.p, epl, e.pm1);
   float gZ = fsel(live, gk * DL * frcp(2.0f * e.u), 0.0f);
-  float coef = fsel(live && e.S > 0.0f, gk * L.a * Dp * 2.0f * e.invS * e.invS, 0.0f);
-  float gX = coef * e.X * e.Y * e.Y;
-  float gY = -coef * e.Y * e.X * e.X;
+  // X/S and Y/S first: (1/S)^2 alone would overflow within ~1e-10 rad of the axis
+  float coef = fsel(live && e.S >= kMinNormal, gk * L.a * Dp * 2.0f, 0.0f);
+  float xs = e.X * e.invS, ys = e.Y * e.invS;
+  float gX = coef * xs * (e.Y * ys);
+  float gY = -coef * ys * (e.X * xs);
   // X = ctau R + stau Q, Y = -stau R + ctau Q, Zc = st P + ct vz, R = ct P - st vz
   float P = fmaf(vx, A.cp, vy * A.sp);
   float Q = fmaf(-vx, A.sp, vy * A.cp);

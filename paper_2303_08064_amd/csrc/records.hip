@@ -96,7 +96,8 @@ __global__ __launch_bounds__(256) void sample_kernel(RecArgs a) {
 }
 
 // Mixture pdf and the gradient of log D with respect to the direction on the
-// sphere: sum_k r_k grad ell_k with r_k = D_k / D, minus its component along v.
+// sphere: sum_k r_k grad ell_k with r_k = D_k / D (each lobe's gradient is
+// formed in the tangent plane of v).
 template <int K>
 __global__ __launch_bounds__(256) void pdf_grad_kernel(RecArgs a) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -113,16 +114,15 @@ __global__ __launch_bounds__(256) void pdf_grad_kernel(RecArgs a) {
     const Eval e = eval_lobe(lb[k], vx, vy, vz, a.eps);
     const float r = fexp(e.ell - logq);
     float hx, hy, hz;
-    dir_grad_lobe(lb[k], e, hx, hy, hz);
+    dir_grad_lobe(lb[k], e, vx, vy, vz, hx, hy, hz);
     gx = fmaf(r, hx, gx);
     gy = fmaf(r, hy, gy);
     gz = fmaf(r, hz, gz);
   }
-  const float dot = fmaf(gx, vx, fmaf(gy, vy, gz * vz));
   a.pdf_out[v] = fexp(logq);
-  a.grad_out[v] = fmaf(-dot, vx, gx);
-  a.grad_out[a.ld + v] = fmaf(-dot, vy, gy);
-  a.grad_out[2 * a.ld + v] = fmaf(-dot, vz, gz);
+  a.grad_out[v] = gx;
+  a.grad_out[a.ld + v] = gy;
+  a.grad_out[2 * a.ld + v] = gz;
 }
 
 template <int K>

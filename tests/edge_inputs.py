@@ -18,12 +18,18 @@ import math
 import numpy as np
 import torch
 
+from oracle import mlp as omlp
 from oracle import nasg as onasg
 from paper_2303_08064_amd import synth
 
 LAMBDAS = (1e-3, 0.1, 1.0, 10.0, 1e2, 1e3, 1e4, math.exp(15.0))
 ECCS = (0.0, 1e-3, 1.0, 1e2, 1e3, math.exp(15.0))
 ANGLES = (0.0, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)
+# A uniformly oriented frame stored in float32 is orthonormal only to ~6e-8,
+# and so is a float32 direction near its axis: below ~1e-4 rad the azimuth
+# about the axis is not determined by the float32 inputs. Those angles are
+# tested on axis-aligned frames, which float32 holds exactly.
+ANGLES_RANDOM = (1e-4, 1e-3, 1e-2, 1e-1)
 U1 = float(np.float32(1.0 - 2.0 ** -24))     # the largest float32 below one
 XI0 = (0.0, 1e-3, 0.5, 0.999, U1)
 XI1 = (0.0, 0.25, 0.5, U1)
@@ -39,19 +45,38 @@ def random_frames(n, rng):
     return z, x
 
 
-def records(lam0, a0, K, rng, eps=0.0, dominant=True):
+def axis_frames(n, rng):
+    """(z, x) [n, 3]: z and x along distinct coordinate axes with random
+    signs, so the float32 record holds an exactly orthonormal frame and the
+    float32 directions near its axis hold their small components to full
+    relative precision."""
+    i = rng.integers(0, 3, n)
+    j = (i + rng.integers(1, 3, n)) % 3
+    z = np.zeros((n, 3))
+    x = np.zeros((n, 3))
+    r = np.arange(n)
+    z[r, i] = rng.choice([-1.0, 1.0], n)
+    x[r, j] = rng.choice([-1.0, 1.0], n)
+    return z, x
+
+
+MINOR = 1e-5      # mixture weight of each other lobe when lobe 0 dominates
+
+
+def records(lam0, a0, K, rng, eps=0.0, dominant=True, frames="random"):
     """[n, K, 9] float32 records; lobe 0 of vertex i has sharpness lam0[i] and
     eccentricity a0[i]; the other lobes are moderate (lambda in [1, 50],
-    a in [0, 5]). dominant: lobe 0 carries all but 1e-6 per other lobe of the
-    mixture weight; else half of it."""
+    a in [0, 5]). dominant: lobe 0 carries all but MINOR per other lobe of
+    the mixture weight; else half of it. frames: "random" (uniformly
+    oriented) or "axis" (``axis_frames``)."""
     n = len(lam0)
-    z, x = random_frames(n * K, rng)
+    z, x = (axis_frames if frames == "axis" else random_frames)(n * K, rng)
     lam = np.exp(rng.uniform(0.0, math.log(50.0), (n, K)))
     a = rng.uniform(0.0, 5.0, (n, K))
     lam[:, 0], a[:, 0] = lam0, a0
     if dominant:
-        A = np.full((n, K), 1e-6)
-        A[:, 0] = 1.0 - 1e-6 * (K - 1)
+        A = np.full((n, K), MINOR)
+        A[:, 0] = 1.0 - MINOR * (K - 1)
     else:
         A = rng.uniform(0.5, 1.5, (n, K))
         A[:, 1:] *= 1.0 / A[:, 1:].sum(1, keepdims=True)
@@ -81,17 +106,18 @@ def meridian_dirs(z, x, t):
     return np.cos(t)[:, None] * z + np.sin(t)[:, None] * y
 
 
-def record_grid(K, eps, seed):
+def record_grid(K, eps, seed, frames="random"):
     """Records and directions over the (lambda, a) grid: for every cell, one
-    vertex per direction in {near +z, near -z} x ANGLES x azimuth
-    {0, pi/4, pi/2, random}, the y meridian at t in {pi/2, 3pi/4, pi - 1e-2,
+    vertex per direction in {near +z, near -z} x ANGLES (ANGLES_RANDOM for
+    uniformly oriented frames) x azimuth {0, pi/4, pi/2, random}, the y meridian at t in {pi/2, 3pi/4, pi - 1e-2,
     pi - 1e-4}, and 8 uniform directions. Lobe 0 is the cell's lobe and
     dominates the mixture in half of the vertices.
+    frames: as in ``records``.
     Returns (rec [n, K, 9] float32, dirs [n, 3] float32, cell [n, 2] int)."""
     rng = synth.rng_for(seed)
     per_lobe = []
     for sign in (1.0, -1.0):
-        for ang in ANGLES:
+        for ang in (ANGLES if frames == "axis" else ANGLES_RANDOM):
             for psi in (0.0, math.pi / 4, math.pi / 2, None):
                 per_lobe.append(("axis", sign, ang, psi))
     for t in (math.pi / 2, 3 * math.pi / 4, math.pi - 1e-2, math.pi - 1e-4):
@@ -107,8 +133,8 @@ def record_grid(K, eps, seed):
     n = len(lam0)
     dom = np.arange(n) % 2 == 0
     rec = np.empty((n, K, 9), np.float32)
-    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True)
-    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False)
+    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True, frames)
+    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False, frames)
     z = rec[:, 0, 0:3].astype(np.float64)
     x = rec[:, 0, 3:6].astype(np.float64)
     dirs = np.empty((n, 3))
@@ -126,7 +152,7 @@ def record_grid(K, eps, seed):
     return rec, dirs.astype(np.float32), np.array(cell)
 
 
-def sample_grid(K, eps, seed):
+def sample_grid(K, eps, seed, frames="random"):
     """Records over the (lambda, a) grid with every combination of the
     extreme uniforms: xi_sel in {0, 1/4, U1} (lobe 0 is chosen by 0 and, when
     it dominates, by 1/4; U1 picks the last lobe), xi0 in XI0, xi1 in XI1,
@@ -144,24 +170,36 @@ def sample_grid(K, eps, seed):
     n = len(lam0)
     dom = np.arange(n) % 2 == 0
     rec = np.empty((n, K, 9), np.float32)
-    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True)
-    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False)
+    rec[dom] = records(np.array(lam0)[dom], np.array(a0)[dom], K, rng, eps, True, frames)
+    rec[~dom] = records(np.array(lam0)[~dom], np.array(a0)[~dom], K, rng, eps, False, frames)
     return rec, np.array(xi, dtype=np.float32), np.array(cell)
 
 
 def scaled_output_weights(mats, seed, max_scale=1000.0, zero_pairs=True):
     """Scale the output layer row by row by log-uniform factors in
     [1, max_scale] so that raw outputs span |o| from ~0 to ~40 (at the
-    default initialisation, |o| per unit scale is ~0.05); with zero_pairs the
+    default initialisation, |o| per unit scale is ~0.05; the log lambda and
+    log a rows of lobes 0 and 1 are calibrated to reach past the clamp);
+    with zero_pairs the
     (sin phi, cos phi) rows of lobe 0 and the (sin tau, cos tau) rows of lobe 1
     are zeroed, so those pairs are exactly (0, 0)."""
     rng = synth.rng_for(seed)
     out = [m.copy() for m in mats]
     W = out[-1].astype(np.float64)
+    K = W.shape[0] // 8
     f = np.exp(rng.uniform(0.0, math.log(max_scale), W.shape[0]))
+    # the log lambda and log a rows of lobes 0 and 1 are scaled so that their
+    # mean output over a reference batch is +25 (lobe 0) and -25 (lobe 1):
+    # past the clamp at +-15 in both directions for most vertices
+    Ws = [torch.tensor(m, dtype=torch.float64) for m in mats]
+    _, pre = omlp.forward(Ws, synth.features(512, synth.rng_for(seed + 1)).T, return_pre=True)
+    h = torch.relu(pre[-2]).numpy()
+    for p in (5, 6):
+        for k, target in ((0, 25.0), (1, -25.0)):
+            row = p * K + k
+            f[row] = target / (h @ W[row]).mean()
     W *= f[:, None]
     if zero_pairs:
-        K = W.shape[0] // 8
         for p, k in ((1, 0), (2, 0), (3, 1), (4, 1)):
             W[p * K + k] = 0.0
     out[-1] = W.astype(np.float32)

@@ -135,9 +135,12 @@ def test_paper_network_bf16_matches_fp32_converged_nll():
     Adam step as for the other networks: BF16's converged held-out NLL within
     2% of FP32's gap to uniform. (At the paper's 4096 samples per step single
     trajectories of either precision differ by up to 0.2 nats after 8000
-    steps, either way round, so that batch does not resolve a 2% bound.)"""
+    steps, either way round, so that batch does not resolve a 2% bound.)
+    Four data streams: single trajectories of this network differ from
+    stream to stream by up to 0.2 nats (measured per-stream means: BF16
+    0.35-0.58, FP32 0.36-0.44), which two streams do not average out."""
     b, f, gap = _converged_nll_gap(("paper_bf16", "paper_f32"), synth.AnisoTarget(8, seed=TARGET_SEED),
-                                   pool_size=150, bsdf=True)
+                                   pool_size=150, bsdf=True, seeds=(7000, 9000, 11000, 13000))
     assert f < math.log(4 * math.pi) - 1.0   # training gained over uniform
     assert abs(gap) <= 0.02
 
