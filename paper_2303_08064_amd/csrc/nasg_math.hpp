@@ -80,7 +80,7 @@ struct LobeAux {
   float loglam, loga;       // clamped raw values
   bool lam_in, a_in;        // raw values inside the clamp range
   float logK;
-  float qlam;               // 2 lam / expm1(2 lam)
+  float omq;                // 1 - 2 lam / expm1(2 lam) = -d log K / d log lam
 };
 
 // A (cos, sin) pair divided by its norm; a zero pair becomes (1, 0).
@@ -99,9 +99,14 @@ __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a
   return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
 }
 
-// The same, also returning 2 lam / expm1(2 lam) = 2 lam e^{-2 lam} / (1 - e^{-2 lam})
-// (the normaliser's lambda derivative) from the same exponential.
-__device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps, float& qlam) {
+// The same, also returning omq = 1 - q with q = 2 lam / expm1(2 lam) =
+// 2 lam e^{-2 lam} / (1 - e^{-2 lam}): d log K / d log lam = q - 1. As lam -> 0,
+// q -> 1 and 1 - q ~ lam, so the difference is lost to cancellation (a
+// relative error of u / lam); for t = 2 lam < 1/2 it comes instead from the
+// series of t / expm1(t) in the Bernoulli numbers:
+//   1 - q = t/2 - t^2/12 + t^4/720 - t^6/30240 + t^8/1209600 - ...,
+// whose next term is below 1e-10 of the sum there.
+__device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps, float& omq) {
   const float x = -2.0f * lam;
   const float ex = fexp(x);                           // e^{-2 lam}
   float p = fmaf(x, 1.0f / 120.0f, 1.0f / 24.0f);    // expm1 series, as in expm1f_
@@ -110,7 +115,12 @@ __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a
   p = fmaf(x, p, 1.0f);
   p = p * x;
   const float one_m = -fsel(fabsf(x) < 0.125f, p, ex - 1.0f);   // 1 - e^{-2 lam}
-  qlam = -x * ex * frcp(one_m);                       // -> 0 as e^{-2 lam} underflows
+  const float t = -x;
+  const float t2 = t * t;
+  float ser = fmaf(t2, 1.0f / 1209600.0f, -1.0f / 30240.0f);
+  ser = fmaf(t2, ser, 1.0f / 720.0f);
+  ser = fmaf(t2 * t2, ser, t * fmaf(t, -1.0f / 12.0f, 0.5f));
+  omq = fsel(t < 0.5f, ser, 1.0f - t * ex * frcp(one_m));   // -> 1 as e^{-2 lam} underflows
   return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
 }
 
@@ -160,7 +170,7 @@ __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L
   X.loga = fminf(fmaxf(o[6], -kLogClamp), kLogClamp);
   L.lam = fexp(X.loglam);
   L.a = amul * fexp(X.loga);
-  X.logK = log_normaliser(L.lam, X.loglam, L.a, eps, X.qlam);
+  X.logK = log_normaliser(L.lam, X.loglam, L.a, eps, X.omq);
   L.logc = 0.0f;
 }
 
@@ -380,7 +390,7 @@ __device__ __forceinline__ void backward_lobe(const Lobe& L, const LobeAux& A, c
   float epl = e.epl;
   float twolam = 2.0f * L.lam;
   // log lambda
-  g[5] = fsel(A.lam_in && live, gk * (twolam * e.E - A.qlam + 1.0f), 0.0f);
+  g[5] = fsel(A.lam_in && live, gk * fmaf(twolam, e.E, A.omq), 0.0f);
   // log a
   float Dp = e.L * fmaf(twolam, epl, 1.0f);
   float ga = L.a * fmaf(e.c2, Dp, 0.5f * frcp(1.0f + eps + L.a));
