@@ -15,6 +15,11 @@ CONFIGS = {
     "c1_bf16": (64, 3, 4, "bf16"),
     "c5_bf16": (128, 4, 32, "bf16"),
     "c5_f32": (128, 4, 32, "f32"),
+    # shallower hidden-64 networks (the kernels take n_hidden in 1..4)
+    "c3nh1_bf16": (64, 1, 16, "bf16"),
+    "c3nh2_bf16": (64, 2, 16, "bf16"),
+    "c3nh1_f32": (64, 1, 16, "f32"),
+    "c3nh2_f32": (64, 2, 16, "f32"),
     # with the selection-probability output (8K + 1 outputs, the blended loss)
     "c2s_f32": (64, 4, 8, "f32"),
     "c3s_bf16": (64, 4, 16, "bf16"),

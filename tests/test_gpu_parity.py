@@ -9,12 +9,7 @@ Tolerances (FP32 path vs the FP64 oracle):
 * sampled direction: |dv| <= 1e-4, vertices whose xi_sel lies within 1e-5 of
   a CDF boundary excluded (either lobe is then a correct choice);
 * loss: rel <= 1e-5;
-* weight gradient, stage by stage (the oracle's chain rule started from the
-  GPU's own raw outputs): per-tensor ||d||/||g|| <= 1e-4; end to end from the
-  features: <= 1e-3. The gap is the conditioning of the azimuth pairs: the
-  frame angle is atan2 of two raw outputs, so when both are near zero its
-  gradient scales as 1/|pair| and FP32 rounding of those outputs (about
-  1e-8 absolute) becomes a relative error of that gradient.
+* weight gradients entry by entry: tests/test_gpu_gradients.py.
 BF16 (operands rounded to bfloat16, FP32 accumulation) is compared with the
 oracle's BF16 emulation; its bounds are stated at each test.
 """
@@ -210,55 +205,6 @@ def _train_batch(B, seed, target_seed=1001):
 def _rel_errors(gpu_list, ref_list):
     return [float(np.linalg.norm(a.numpy() - b.numpy()) / np.linalg.norm(b.numpy()))
             for a, b in zip(gpu_list, ref_list)]
-
-
-@pytest.mark.parametrize("name,B,seed", [("c1_f32", 4096, 10), ("c2_f32", B_RAGGED, 10),
-                                         ("c2_f32", 4096, 3), ("c3_f32", 777, 10), ("c5_f32", 777, 10)])
-def test_loss_grad_f32(name, B, seed):
-    K = CONFIGS[name][2]
-    g, mats = make_guide(name, out_scale=2.0)
-    feat, dirs, w = _train_batch(B, seed)
-    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
-    torch.cuda.synchronize()
-    W = w64(mats)
-    L, grads = otrain.loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), K)
-    Lg = float(g.stats[0])
-    assert abs(Lg - L) <= 1e-5 * abs(L), (Lg, L)
-    assert abs(float(g.stats[1]) - w.astype(np.float64).sum()) <= 1e-9 * w.sum()
-    gg = g.split(g.grad.cpu())
-    # stage by stage: NASG backward and MLP backward from the GPU's raw outputs
-    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
-    g_raw = otrain.raw_output_grad(raw, dirs.T, w.astype(np.float64), K)
-    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
-    errs = _rel_errors(gg, staged)
-    assert max(errs) < 1e-4, errs
-    errs_e2e = _rel_errors(gg, grads)
-    assert max(errs_e2e) < 1e-3, errs_e2e
-
-
-@pytest.mark.parametrize("name,B", [("c3_bf16", 2083), ("c2_bf16", 2083), ("c5_bf16", 2083), ("c5_bf16", 20000)])
-def test_loss_grad_bf16(name, B):
-    """BF16 operands (weights, activations, backward deltas) with FP32
-    accumulation vs the oracle's BF16-emulated forward differentiated in FP64:
-    per-tensor ||d||/||g|| <= 2e-2 (the deltas' BF16 rounding, 2^-9 relative
-    per element, is the dominant term) and the loss within 1e-3 relative.
-    The hidden-128 network runs its two backward groups at once up to 16384
-    samples (on 256 CUs) and one after the other above: both are checked."""
-    K = CONFIGS[name][2]
-    g, mats = make_guide(name, out_scale=2.0, max_batch=max(B, 1 << 18))
-    feat, dirs, w = _train_batch(B, 11)
-    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w))
-    torch.cuda.synchronize()
-    W = w64(mats)
-    L, grads = otrain.loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), K, bf16=True)
-    assert abs(float(g.stats[0]) - L) <= 1e-3 * abs(L)
-    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
-    g_raw = otrain.raw_output_grad(raw, dirs.T, w.astype(np.float64), K)
-    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw, bf16=True)
-    errs = _rel_errors(g.split(g.grad.cpu()), staged)
-    assert max(errs) < 2e-2, errs
-    errs_e2e = _rel_errors(g.split(g.grad.cpu()), grads)
-    assert max(errs_e2e) < 5e-2, errs_e2e
 
 
 @pytest.mark.parametrize("name", ["c2_f32", "c3_bf16", "c5_bf16", "c5_f32"])

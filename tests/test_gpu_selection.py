@@ -5,10 +5,9 @@ Networks with 8K + 1 outputs: row 8K is the selection logit, c = sigmoid.
 The loss is e KL(p || q_hat) + (1 - e) KL(p || q), q_hat = c q + (1 - c) p_fs,
 estimated per sample with the weight w = p / q_hat (supplied) and the BSDF
 pdf p_fs at the training direction (supplied; here a Lambertian lobe about
-the vertex normal). Tolerances as in test_gpu_parity: FP32 raw outputs 1e-5
-per row; c 1e-6; loss 1e-5 relative; gradient 1e-4 stage-wise (the oracle's
-chain rule from the GPU's own raw outputs), 1e-3 end to end; BF16 against
-the oracle's BF16 emulation 2e-2 stage-wise.
+the vertex normal). Tolerances: FP32 raw outputs 1e-5 per row; c 1e-6. The
+blended loss's weight gradients, entry by entry, are in
+tests/test_gpu_gradients.py (c1s_f32, c2s_f32, c3s_bf16, the paper network).
 """
 
 import numpy as np
@@ -66,47 +65,6 @@ def test_forward_and_selection_output(name):
     dd = d.cpu().numpy().T.astype(np.float64)
     lq = onasg.mixture_log_pdf(torch.tensor(dd), lob).numpy()
     assert np.median(np.abs(np.log(pdf.cpu().numpy()) - lq)) < 1e-5
-
-
-@pytest.mark.parametrize("name,B", [("c2s_f32", 1000), ("c1s_f32", 4096)])
-def test_blended_loss_grad_f32(name, B):
-    K = CONFIGS[name][2]
-    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E)
-    feat, dirs, w, pdf = _batch(B, 42)
-    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
-    torch.cuda.synchronize()
-    W = w64(mats)
-    L, grads = otrain.blended_loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
-    assert abs(float(g.stats[0]) - L) <= 1e-5 * abs(L), (float(g.stats[0]), L)
-    gg = [t.numpy() for t in g.split(g.grad.cpu())]
-    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
-    g_raw = otrain.blended_raw_output_grad(raw, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
-    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw)
-    errs = [_rel(a, b.numpy()) for a, b in zip(gg, staged)]
-    assert max(errs) < 1e-4, errs
-    # the selection row on its own (it is one row of the output layer)
-    assert _rel(gg[-1][-1], staged[-1][-1].numpy()) < 1e-4
-    errs_e2e = [_rel(a, b.numpy()) for a, b in zip(gg, grads)]
-    assert max(errs_e2e) < 1e-3, errs_e2e
-
-
-def test_blended_loss_grad_bf16():
-    name, K = "c3s_bf16", 16
-    g, mats = make_guide(name, out_scale=2.0, mis_fraction=E)
-    feat, dirs, w, pdf = _batch(2048 + 35, 43)
-    g.loss_grad(to_dev(feat), to_dev(dirs), to_dev(w), bsdf_pdf=to_dev(pdf))
-    torch.cuda.synchronize()
-    W = w64(mats)
-    L, grads = otrain.blended_loss_and_grad(W, feat.T, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K,
-                                            e=E, bf16=True)
-    assert abs(float(g.stats[0]) - L) <= 1e-3 * abs(L)
-    raw = g.forward_raw(to_dev(feat)).cpu().numpy().T.astype(np.float64)
-    g_raw = otrain.blended_raw_output_grad(raw, dirs.T, w.astype(np.float64), pdf.astype(np.float64), K, e=E)
-    staged = otrain.weight_grad_from_raw_grad(W, feat.T, g_raw, bf16=True)
-    gg = [t.numpy() for t in g.split(g.grad.cpu())]
-    errs = [_rel(a, b.numpy()) for a, b in zip(gg, staged)]
-    assert max(errs) < 2e-2, errs
-    assert max(_rel(a, b.numpy()) for a, b in zip(gg, grads)) < 5e-2
 
 
 @pytest.mark.parametrize("name,base", [("c2s_f32", "c2_f32"), ("c3s_bf16", "c3_bf16")])
