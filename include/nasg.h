@@ -13,7 +13,8 @@
  * --------------------------------
  * - Every array argument is a DEVICE pointer owned by the caller. The library
  *   never allocates, frees or retains device memory beyond what the caller
- *   passes in; it never synchronises the host.
+ *   passes in (apart from the fixed scratch array of
+ *   nasg_train_step_noalloc); it never synchronises the host.
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Every compute call is asynchronous on that stream.
  * - Vertex arrays are structure-of-arrays with leading dimension `ld`
@@ -183,6 +184,25 @@ nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream);
 /* nasg_loss_grad followed by nasg_adam_step. */
 nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
                             const float* bsdf_pdf, int64_t ld, int64_t B, void* stream);
+
+/* nasg_train_step without the caller's workspace, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation). The same kernels and results as
+ * nasg_train_step, bit for bit; the step's scratch (per-workgroup gradient
+ * partials, loss and gradient-norm partials, the step snapshot) lives in a
+ * 24 MiB array that the library holds on each GPU it runs on until the
+ * process ends (its address is looked up once per device by nasg_create).
+ * Every call on a GPU shares that GPU's array and needs none of its
+ * previous contents: calls that overlap on one GPU (on different streams, or
+ * with nasg_train_step_noalloc of another context) race and must be
+ * ordered by the caller. The state arrays (weights, moments, grad, flags,
+ * stats) are still the context's.
+ * Serves hidden-64 networks (NASG_E_ARG for hidden 128); NASG_E_SHAPE if the
+ * step's workspace would exceed the scratch (not the case for any compiled
+ * hidden-64 network); NASG_E_ARG if the current device is not the context's.
+ * Arguments and the other errors as nasg_train_step. */
+nasg_status nasg_train_step_noalloc(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
+                                    const float* bsdf_pdf, int64_t ld, int64_t B, void* stream);
 
 /* The blend ramp b of Sec. 5 (host only): 0 at the start, raised by 1/B after
  * every M rendered images, capped at 1 (the paper uses M = 4, B = 64).

@@ -19,6 +19,7 @@ EXPORTED = [
     "nasg_num_weights", "nasg_packed_bytes", "nasg_workspace_bytes", "nasg_create", "nasg_destroy",
     "nasg_last_error", "nasg_pack", "nasg_forward", "nasg_query", "nasg_pdf", "nasg_sample",
     "nasg_loss_grad", "nasg_adam_step", "nasg_train_step", "nasg_blend_ramp", "nasg_pdf_grad",
+    "nasg_train_step_noalloc",
 ]
 
 
@@ -77,6 +78,7 @@ def load():
         "nasg_loss_grad": (S, [P, P, P, P, P, I64, I64, P]),
         "nasg_adam_step": (S, [P, P]),
         "nasg_train_step": (S, [P, P, P, P, P, I64, I64, P]),
+        "nasg_train_step_noalloc": (S, [P, P, P, P, P, I64, I64, P]),
         "nasg_blend_ramp": (ctypes.c_float, [I64, ctypes.c_int32, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "kernels.hpp"
@@ -131,7 +132,41 @@ struct nasg_ctx {
   NetDims d;
   Workspace ws;
   int num_cus;
+  int device;
 };
+
+namespace {
+
+// ---- scratch of the entry point without allocation ----
+// nasg_train_step_noalloc keeps the training step's workspace (per-workgroup
+// gradient partials, loss and gradient-norm partials, the step snapshot) in
+// this file-scope device array instead of the caller's workspace. Hidden-64
+// networks need at most 256 partials of 21184 weights (K = 16 with the
+// selection output): 21.7 MB of the 24 MiB. In host code `scratch` only
+// names the symbol; its device address, one per GPU, comes from
+// hipGetSymbolAddress (scratch_ptr), which every use goes through.
+constexpr size_t kScratchBytes = (size_t)24 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on `dev` (the current device), looked up once.
+hipError_t scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -170,12 +205,16 @@ nasg_status nasg_create(const nasg_config* cfg, const nasg_state* st, nasg_ctx**
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(fn, e);
+  void* scr = nullptr;
+  e = scratch_ptr(dev, &scr);   // once per device: the allocation-free entry point's scratch
+  if (e != hipSuccess) return hip_fail(fn, e);
   nasg_ctx* c = new nasg_ctx;
   c->cfg = *cfg;
   c->st = *st;
   c->d = dims_of(cfg);
   c->ws = carve(cfg);
   c->num_cus = cus > 0 ? cus : 1;
+  c->device = dev;
   e = launch_pack(st->w, st->wpack, c->d, cfg->precision, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
@@ -308,9 +347,9 @@ nasg_status nasg_sample(nasg_ctx* ctx, const float* rec, const float* xi, int64_
   return e == hipSuccess ? NASG_OK : hip_fail(fn, e);
 }
 
-static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
+// ws: the workspace base (the caller's, or the scratch array's address)
+static nasg_status adam_only(nasg_ctx* ctx, const char* fn, unsigned char* ws, void* stream) {
   const nasg_state& s = ctx->st;
-  unsigned char* ws = static_cast<unsigned char*>(s.workspace);
   AdamArgs a;
   a.w = s.w;
   a.m = s.adam_m;
@@ -341,7 +380,7 @@ static nasg_status adam_only(nasg_ctx* ctx, const char* fn, void* stream) {
 // the loss and gradient launches of nasg_loss_grad and nasg_train_step; fn
 // names the entry point in error messages
 static nasg_status loss_grad(nasg_ctx* ctx, const char* fn, const float* feat, const float* dir, const float* w,
-                             const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
+                             const float* bsdf_pdf, int64_t ld, int64_t B, unsigned char* ws, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
   NASG_TRY(check_batch(fn, ld, B));
   if (B > ctx->cfg.max_batch) return fail(NASG_E_SHAPE, fn, "B > max_batch");
@@ -352,7 +391,6 @@ static nasg_status loss_grad(nasg_ctx* ctx, const char* fn, const float* feat, c
   if (ctx->cfg.selection == 1) NASG_TRY(check_ptr(fn, bsdf_pdf, "bsdf_pdf"));
   else if (bsdf_pdf != nullptr) return fail(NASG_E_ARG, fn, "bsdf_pdf needs a network with the selection output");
   const nasg_state& s = ctx->st;
-  unsigned char* ws = static_cast<unsigned char*>(s.workspace);
   const bool large = is_large(&ctx->cfg);
   const int n_wg = large ? large_train_workgroups(B, ctx->num_cus, ctx->cfg.precision)
                          : train_workgroups(B, ctx->num_cus);
@@ -416,18 +454,40 @@ static nasg_status loss_grad(nasg_ctx* ctx, const char* fn, const float* feat, c
 
 nasg_status nasg_loss_grad(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
                            const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
-  return loss_grad(ctx, "nasg_loss_grad", feat, dir, w, bsdf_pdf, ld, B, stream);
+  if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_loss_grad", "ctx is NULL");
+  return loss_grad(ctx, "nasg_loss_grad", feat, dir, w, bsdf_pdf, ld, B,
+                   static_cast<unsigned char*>(ctx->st.workspace), stream);
 }
 
 nasg_status nasg_adam_step(nasg_ctx* ctx, void* stream) {
   if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_adam_step", "ctx is NULL");
-  return adam_only(ctx, "nasg_adam_step", stream);
+  return adam_only(ctx, "nasg_adam_step", static_cast<unsigned char*>(ctx->st.workspace), stream);
 }
 
 nasg_status nasg_train_step(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
                             const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
-  NASG_TRY(loss_grad(ctx, "nasg_train_step", feat, dir, w, bsdf_pdf, ld, B, stream));
-  return adam_only(ctx, "nasg_train_step", stream);
+  if (ctx == nullptr) return fail(NASG_E_ARG, "nasg_train_step", "ctx is NULL");
+  unsigned char* ws = static_cast<unsigned char*>(ctx->st.workspace);
+  NASG_TRY(loss_grad(ctx, "nasg_train_step", feat, dir, w, bsdf_pdf, ld, B, ws, stream));
+  return adam_only(ctx, "nasg_train_step", ws, stream);
+}
+
+nasg_status nasg_train_step_noalloc(nasg_ctx* ctx, const float* feat, const float* dir, const float* w,
+                                    const float* bsdf_pdf, int64_t ld, int64_t B, void* stream) {
+  static const char* fn = "nasg_train_step_noalloc";
+  if (ctx == nullptr) return fail(NASG_E_ARG, fn, "ctx is NULL");
+  if (is_large(&ctx->cfg)) return fail(NASG_E_ARG, fn, "serves hidden-64 networks only");
+  if (ctx->ws.total > kScratchBytes) return fail(NASG_E_SHAPE, fn, "the step's workspace exceeds the 24 MiB scratch");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(fn, e);
+  if (dev != ctx->device) return fail(NASG_E_ARG, fn, "the current device is not the one the context was created on");
+  void* scr = nullptr;
+  e = scratch_ptr(dev, &scr);
+  if (e != hipSuccess) return hip_fail(fn, e);
+  unsigned char* ws = static_cast<unsigned char*>(scr);
+  NASG_TRY(loss_grad(ctx, fn, feat, dir, w, bsdf_pdf, ld, B, ws, stream));
+  return adam_only(ctx, fn, ws, stream);
 }
 
 float nasg_blend_ramp(int64_t frames_done, int32_t M, int32_t B) {
