@@ -133,6 +133,7 @@ struct nasg_ctx {
   Workspace ws;
   int num_cus;
   int device;
+  int q_per_cu[2];   // resident query kernel's workgroups per CU (query, raw forward)
 };
 
 namespace {
@@ -215,6 +216,15 @@ nasg_status nasg_create(const nasg_config* cfg, const nasg_state* st, nasg_ctx**
   c->ws = carve(cfg);
   c->num_cus = cus > 0 ? cus : 1;
   c->device = dev;
+  c->q_per_cu[0] = c->q_per_cu[1] = 1;
+  if (query_is_resident(c->d, cfg->precision)) {
+    for (int mode = 0; mode < 2 && e == hipSuccess; ++mode)
+      e = query_workgroups_per_cu(c->d, cfg->precision, mode, (int)query_lds_bytes(cfg), &c->q_per_cu[mode]);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(fn, e);
+    }
+  }
   e = launch_pack(st->w, st->wpack, c->d, cfg->precision, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
@@ -287,6 +297,7 @@ static nasg_status run_query(nasg_ctx* ctx, const char* fn, const float* feat, c
   a.sel = ctx->d.S;
   a.amul = ctx->cfg.isotropic ? 0.0f : 1.0f;
   a.num_cus = ctx->num_cus;
+  a.per_cu = ctx->q_per_cu[mode];
   hipError_t e = query_is_resident(ctx->d, ctx->cfg.precision)
                      ? launch_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream)
                      : launch_large_query(a, ctx->d, ctx->cfg.precision, mode, (hipStream_t)stream);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "layout.hpp"
 #include "nasg_math.hpp"
 
@@ -120,5 +122,18 @@ __device__ __forceinline__ void lds_dma(void* lds, const void* src, int bytes) {
 // s_waitcnt vmcnt(0): every vector-memory load of this wave, including the
 // direct-to-LDS copies, has completed (expcnt and lgkmcnt left unconstrained).
 __device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Raises KERN's dynamic-LDS limit to `bytes` (the largest footprint any of
+// its launches uses) once per process; thread safe, and every later call
+// returns the first call's status.
+template <auto KERN>
+inline hipError_t set_max_lds_once(size_t bytes) {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [bytes] {
+    err = hipFuncSetAttribute((const void*)KERN, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  });
+  return err;
+}
 
 }  // namespace nasg

@@ -144,13 +144,12 @@ __device__ __forceinline__ float train_epilogue(const float (&out)[MTO][4], floa
   return lterm;
 }
 
-// Guiding query of one vertex: decode, inverse-CDF lobe choice, App. C
-// sample, mixture pdf at the sample. Returns log q; v receives the unit
-// direction; lb receives the decoded lobes (for the optional record store).
+// A query's decode of one vertex's lobes (Tab. "decoding"): frames,
+// lambda, a and log c = log(A_k / K_k) into lb, the mixture weights A_k
+// (softmax of the K logits) into A.
 template <int KQ, int MTO>
-__device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], float xi_sel, float xi0, float xi1,
-                                                float xi2, float eps, int g, int c, Lobe (&lb)[KQ], float& vx,
-                                                float& vy, float& vz, float amul = 1.0f) {
+__device__ __forceinline__ void query_decode(const float (&out)[MTO][4], float eps, Lobe (&lb)[KQ], float (&A)[KQ],
+                                             float amul) {
   float logK[KQ], alpha[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
@@ -174,23 +173,45 @@ __device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], floa
   se = quad_sum(se);
   const float lse = mx + flog(se);
   const float inv_se = frcp(se);
-  float A[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     lb[q].logc = (alpha[q] - lse) - logK[q];
     A[q] = ea[q] * inv_se;
   }
-  const int ksel = select_lobe<KQ>(A, xi_sel, g, c);
-  const Lobe s = broadcast_lobe<KQ>(lb, ksel, c);
+}
+
+// One App. C sample from lobe s, normalised to unit length.
+__device__ __forceinline__ void sample_unit(const Lobe& s, float xi0, float xi1, float xi2, float eps, float& vx,
+                                            float& vy, float& vz) {
   sample_lobe(s, xi0, xi1, xi2, eps, vx, vy, vz);
   const float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
   vx *= inv;
   vy *= inv;
   vz *= inv;
+}
+
+// log q at a unit direction: the lane's lobes, then the vertex's 4 lanes.
+template <int KQ>
+__device__ __forceinline__ float query_log_pdf(const Lobe (&lb)[KQ], float vx, float vy, float vz, float eps) {
   float ell[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) ell[q] = eval_lobe_ell(lb[q], vx, vy, vz, eps);
   return mixture_lse<KQ>(ell);
+}
+
+// Guiding query of one vertex: decode, inverse-CDF lobe choice, App. C
+// sample, mixture pdf at the sample. Returns log q; v receives the unit
+// direction; lb receives the decoded lobes (for the optional record store).
+template <int KQ, int MTO>
+__device__ __forceinline__ float query_epilogue(const float (&out)[MTO][4], float xi_sel, float xi0, float xi1,
+                                                float xi2, float eps, int g, int c, Lobe (&lb)[KQ], float& vx,
+                                                float& vy, float& vz, float amul = 1.0f) {
+  float A[KQ];
+  query_decode<KQ, MTO>(out, eps, lb, A, amul);
+  const int ksel = select_lobe<KQ>(A, xi_sel, g, c);
+  const Lobe s = broadcast_lobe<KQ>(lb, ksel, c);
+  sample_unit(s, xi0, xi1, xi2, eps, vx, vy, vz);
+  return query_log_pdf<KQ>(lb, vx, vy, vz, eps);
 }
 
 }  // namespace nasg

@@ -43,6 +43,7 @@ struct QueryArgs {
   int sel;               // 1: the network has the selection output (8K + 1 rows)
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
+  int per_cu;            // resident query kernel: workgroups per CU at this LDS footprint
 };
 
 struct RecArgs {
@@ -91,6 +92,7 @@ struct LargeTrainArgs {
   int64_t n_weights;
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
+  int per_cu;            // resident query kernel: workgroups per CU at this LDS footprint
 };
 
 struct ReduceArgs {
@@ -192,6 +194,9 @@ __device__ __forceinline__ float mixture_lse(const float (&ell)[KQ]) {
 hipError_t launch_query(const QueryArgs& a, const NetDims& d, int prec, int mode, hipStream_t st);
 // the network's queries run the LDS-resident query kernel
 bool query_is_resident(const NetDims& d, int prec);
+// workgroups per CU of the resident query kernel (mode 0 query, 1 raw
+// forward) at `lds_bytes` of LDS; also raises the kernel's LDS limit
+hipError_t query_workgroups_per_cu(const NetDims& d, int prec, int mode, int lds_bytes, int* per_cu);
 hipError_t launch_pdf(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_sample(const RecArgs& a, int K, hipStream_t st);
 hipError_t launch_pdf_grad(const RecArgs& a, int K, hipStream_t st);

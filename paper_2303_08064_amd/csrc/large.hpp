@@ -1001,21 +1001,13 @@ void bwd_f32_kernel(LargeTrainArgs a) {
 }
 
 // ------------------------------------------------------------ launchers ----
-template <typename Kern>
-static hipError_t set_lds(Kern kern, size_t bytes) {
-  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 template <int H, int K, int PREC, int SEL, int ENC>
 static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t st) {
   const size_t shmem = LargeLds<H, K, PREC, SEL, ENC>::fwd;
   auto kern = mode == 0 ? large_query_kernel<H, K, PREC, SEL, ENC, 0> : large_query_kernel<H, K, PREC, SEL, ENC, 1>;
-  static bool attr[2] = {false, false};
-  if (!attr[mode]) {
-    hipError_t e = set_lds(kern, shmem);
-    if (e != hipSuccess) return e;
-    attr[mode] = true;
-  }
+  hipError_t e = mode == 0 ? set_max_lds_once<large_query_kernel<H, K, PREC, SEL, ENC, 0>>(shmem)
+                           : set_max_lds_once<large_query_kernel<H, K, PREC, SEL, ENC, 1>>(shmem);
+  if (e != hipSuccess) return e;
   const int64_t n_tiles = (a.B + kWGV - 1) / kWGV;
   const int64_t cap = 2LL * a.num_cus;
   const int grid = (int)(n_tiles < cap ? (n_tiles < 1 ? 1 : n_tiles) : cap);
@@ -1026,18 +1018,14 @@ static hipError_t launch_large_query_t(const QueryArgs& a, int mode, hipStream_t
 template <int H, int K, int PREC, int SEL, int ENC>
 static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_grad, hipStream_t st) {
   typedef LargeLds<H, K, PREC, SEL, ENC> Lds;
-  static bool attr = false;
   if constexpr (PREC == 1) {
     auto k_bwd0 = bwd_bf16_kernel<H, K, SEL, ENC, 0>;
     auto k_bwd1 = bwd_bf16_kernel<H, K, SEL, ENC, 1>;
     auto k_both = bwd_bf16_kernel<H, K, SEL, ENC, 2>;
-    if (!attr) {
-      hipError_t e = set_lds(k_bwd0, Lds::bwd);
-      if (e == hipSuccess) e = set_lds(k_bwd1, Lds::bwd);
-      if (e == hipSuccess) e = set_lds(k_both, Lds::bwd);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    hipError_t e = set_max_lds_once<bwd_bf16_kernel<H, K, SEL, ENC, 0>>(Lds::bwd);
+    if (e == hipSuccess) e = set_max_lds_once<bwd_bf16_kernel<H, K, SEL, ENC, 1>>(Lds::bwd);
+    if (e == hipSuccess) e = set_max_lds_once<bwd_bf16_kernel<H, K, SEL, ENC, 2>>(Lds::bwd);
+    if (e != hipSuccess) return e;
     const int64_t n_tiles = (a.B + kBwdV - 1) / kBwdV;
     if (n_tiles <= n_wg && 2 * n_wg <= a.num_cus) {
       // a small batch: one tile per workgroup and one workgroup per CU for
@@ -1053,13 +1041,10 @@ static hipError_t launch_large_train_t(const LargeTrainArgs& a, int n_wg, int n_
     auto k_grad = gradout_kernel<H, K, SEL, ENC>;
     auto k_bwd0 = bwd_f32_kernel<H, K, SEL, ENC, 0>;
     auto k_bwd1 = bwd_f32_kernel<H, K, SEL, ENC, 1>;
-    if (!attr) {
-      hipError_t e = set_lds(k_grad, Lds::fwd);
-      if (e == hipSuccess) e = set_lds(k_bwd0, Lds::bwd);
-      if (e == hipSuccess) e = set_lds(k_bwd1, Lds::bwd);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    hipError_t e = set_max_lds_once<gradout_kernel<H, K, SEL, ENC>>(Lds::fwd);
+    if (e == hipSuccess) e = set_max_lds_once<bwd_f32_kernel<H, K, SEL, ENC, 0>>(Lds::bwd);
+    if (e == hipSuccess) e = set_max_lds_once<bwd_f32_kernel<H, K, SEL, ENC, 1>>(Lds::bwd);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_grad, dim3(n_grad), dim3(256), Lds::fwd, st, a);
     hipLaunchKernelGGL(k_bwd0, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);
     hipLaunchKernelGGL(k_bwd1, dim3(n_wg), dim3(Lds::bwd_threads), Lds::bwd, st, a);

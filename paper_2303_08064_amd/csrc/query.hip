@@ -13,11 +13,17 @@
 
 namespace nasg {
 
-// Waves per SIMD the query kernel is compiled for: three for the hidden-64
-// networks (VALU-bound epilogue), one for their raw forward; two for the
-// hidden-128 network, whose 132 KiB of forward weights leave room for one
+// The hidden-64 BF16 networks' queries sample one vertex per lane (four
+// blocks per wave pass; the four blocks' lobes take 144 registers, so two
+// waves per SIMD). Their FP32 queries keep one block per pass and three
+// waves per SIMD (the four blocks' lobes and the FP32 forward do not fit two
+// waves' registers); the raw forwards run one wave per SIMD; the hidden-128
+// network two, its 132 KiB of forward weights leaving room for one
 // workgroup per CU.
-constexpr int query_waves_per_eu(int H, int MODE) { return H == 64 ? (MODE == 0 ? 3 : 1) : 2; }
+constexpr bool query_four(int H, int K, int MODE, int PREC) { return H == 64 && K != 8 && MODE == 0 && PREC == 1; }
+constexpr int query_waves_per_eu(int H, int K, int MODE, int PREC) {
+  return H == 64 ? (MODE == 0 ? (query_four(H, K, MODE, PREC) ? 2 : 3) : 1) : 2;
+}
 
 // The rest of a query for one 16-vertex block from its raw outputs: decode,
 // choose a lobe, sample, evaluate the pdf and store (MODE 0), or store the
@@ -58,16 +64,82 @@ __device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&o
     // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
     if (S == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[MTO - 1][0]));
   }
-  if (a.rec_out != nullptr && valid) {
-    float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+  if (a.rec_out != nullptr && valid) store_records<KQ>(a, lb, v, g);
+}
+
+// Records of one 16-vertex block's lobes (optional output of a query).
+template <int KQ>
+__device__ __forceinline__ void store_records(const QueryArgs& a, const Lobe (&lb)[KQ], int64_t v, int g) {
+  constexpr int K = 4 * KQ;
+  float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      const int k = g * KQ + q;
-      const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz,
-                             lb[q].lam, lb[q].a, lb[q].logc};
+  for (int q = 0; q < KQ; ++q) {
+    const int k = g * KQ + q;
+    const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz, lb[q].lam, lb[q].a, lb[q].logc};
 #pragma unroll
-      for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
-    }
+    for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
+  }
+}
+
+// The query (MODE 0) of the hidden-64 networks, one sample per lane: a wave
+// takes four 16-vertex blocks per pass. For each block it runs the forward,
+// decodes the lobes (lane (g, c): vertex c, lobes g*K/4 ..), chooses a lobe
+// per vertex and moves the chosen lobe to lane (block, c). Then every lane
+// samples the vertex (block g, vertex c) once, instead of the four lanes of
+// a vertex each repeating the sample; the directions go back to the lanes
+// that hold each block's lobes for the pdf, and lane (g, c) stores the
+// direction and pdf of vertex (g, c). Per vertex, the same operations in the
+// same order as the one-block pass, so the same results bit for bit.
+template <int H, int K, int PREC, int S, int E, int NW>
+__device__ __forceinline__ void query_four_blocks(const QueryArgs& a, const typename Forward<H, K, PREC, 4, S, E>::W* wts,
+                                                  int64_t tile, int lane) {
+  typedef Mlp<H, K, PREC, E> M;
+  typedef Forward<H, K, PREC, 4, S, E> F;
+  constexpr int KQ = K / 4;
+  constexpr int MTO = F::MTO;
+  const int g = lane >> 4, c = lane & 15;
+  Lobe lb[4][KQ];
+  Lobe ch = {};
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t v = tile * (4 * kTileV) + b * kTileV + c;
+    const bool valid = v < a.B;
+    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    float out[MTO][4];
+    F::run_query(wts, a.nh, x, out, lane);
+    float A[KQ];
+    query_decode<KQ, MTO>(out, a.eps, lb[b], A, a.amul);
+    const float xs = valid ? a.xi[v] : 0.0f;
+    const int k = select_lobe<KQ>(A, xs, g, c);
+    const Lobe r = broadcast_lobe<KQ>(lb[b], k, c);
+    if (g == b) ch = r;
+    // selection probability c = sigmoid(o[8K]) (Tab. "decoding")
+    if (S == 1 && a.sel_out != nullptr && valid && g == 0) a.sel_out[v] = frcp(1.0f + fexp(-out[MTO - 1][0]));
+    if (a.rec_out != nullptr && valid) store_records<KQ>(a, lb[b], v, g);
+  }
+  const int64_t vm = tile * (4 * kTileV) + lane;   // vertex (block g, c)
+  const bool mine = vm < a.B;
+  float xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
+  if (mine) {
+    xi0 = a.xi[a.ld + vm];
+    xi1 = a.xi[2 * a.ld + vm];
+    xi2 = a.xi[3 * a.ld + vm];
+  }
+  float vx, vy, vz;
+  sample_unit(ch, xi0, xi1, xi2, a.eps, vx, vy, vz);
+  float logq = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int src = b * kTileV + c;
+    const float bx = __shfl(vx, src), by = __shfl(vy, src), bz = __shfl(vz, src);
+    const float lq = query_log_pdf<KQ>(lb[b], bx, by, bz, a.eps);
+    if (g == b) logq = lq;
+  }
+  if (mine) {
+    a.dir_out[vm] = vx;
+    a.dir_out[a.ld + vm] = vy;
+    a.dir_out[2 * a.ld + vm] = vz;
+    a.pdf_out[vm] = fexp(logq);
   }
 }
 
@@ -76,7 +148,7 @@ __device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&o
 // the encoded input; NB: 16-vertex blocks per wave per pass (NB > 1 shares
 // every weight fragment read among NB MFMAs); NW: waves per workgroup.
 template <int H, int K, int PREC, int MODE, int S, int E, int NB, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(query_waves_per_eu(H, MODE))))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(query_waves_per_eu(H, K, MODE, PREC))))
 void query_kernel(QueryArgs a) {
   constexpr int NHMAX = 4;
   typedef Mlp<H, K, PREC, E> M;
@@ -95,6 +167,12 @@ void query_kernel(QueryArgs a) {
   const int lane = lane_id();
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
+  if constexpr (query_four(H, K, MODE, PREC)) {
+    const int64_t n_tiles = (a.B + 4 * kTileV - 1) / (4 * kTileV);
+    for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += (int64_t)gridDim.x * NW)
+      query_four_blocks<H, K, PREC, S, E, NW>(a, wts, tile, lane);
+    return;
+  }
   constexpr int TV = kTileV * NB;   // vertices per wave pass
   const int64_t n_tiles = (a.B + TV - 1) / TV;
   for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += (int64_t)gridDim.x * NW) {
@@ -122,26 +200,32 @@ void query_kernel(QueryArgs a) {
 template <int H, int K, int PREC, int S, int E, int NB, int NW>
 static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
   auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S, E, NB, NW> : query_kernel<H, K, PREC, 1, S, E, NB, NW>;
-  constexpr int threads = 64 * NW;
-  // occupancy depends on the LDS footprint; cache it per (mode, footprint)
-  static int cached_bytes[2] = {-1, -1};
-  static int cached_per_cu[2] = {1, 1};
-  if (cached_bytes[mode] != a.lds_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
-    if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, a.lds_bytes);
-    if (e != hipSuccess) return e;
-    cached_per_cu[mode] = per_cu < 1 ? 1 : per_cu;
-    cached_bytes[mode] = a.lds_bytes;
-  }
-  const int64_t n_tiles = (a.B + kTileV * NB - 1) / (kTileV * NB);
+  const int TV = kTileV * (query_four(H, K, mode, PREC) ? 4 : NB);   // vertices per wave pass
+  const int64_t n_tiles = (a.B + TV - 1) / TV;
   const int64_t want = (n_tiles + NW - 1) / NW;
-  const int64_t cap = (int64_t)cached_per_cu[mode] * a.num_cus;
+  const int64_t cap = (int64_t)(a.per_cu < 1 ? 1 : a.per_cu) * a.num_cus;
   int grid = (int)(want < cap ? want : cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), a.lds_bytes, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), a.lds_bytes, st, a);
   return hipGetLastError();
+}
+
+// The LDS limit is raised once to the footprint of the network shape's
+// deepest variant (4 hidden layers); the occupancy is that of the caller's
+// footprint.
+template <int H, int K, int PREC, int S, int E, int NB, int NW>
+static hipError_t occupancy_s(int mode, int lds_bytes, int* per_cu) {
+  const NetDims dmax{H, 4, K, S, E};
+  const int max_bytes = PREC == 1 ? (int)Bf16Layout{dmax}.fwd_elems() * 2 : (int)F32Layout{dmax}.total_elems() * 4;
+  if (lds_bytes > max_bytes) return hipErrorInvalidValue;
+  hipError_t e = mode == 0 ? set_max_lds_once<query_kernel<H, K, PREC, 0, S, E, NB, NW>>(max_bytes)
+                           : set_max_lds_once<query_kernel<H, K, PREC, 1, S, E, NB, NW>>(max_bytes);
+  if (e != hipSuccess) return e;
+  auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S, E, NB, NW> : query_kernel<H, K, PREC, 1, S, E, NB, NW>;
+  int n = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 64 * NW, lds_bytes);
+  *per_cu = n < 1 ? 1 : n;
+  return e;
 }
 
 template <int H, int K, int PREC>
@@ -159,6 +243,21 @@ hipError_t launch_query(const QueryArgs& a, const NetDims& d, int prec, int mode
 #define NASG_CASE(h, k, p, s, e)                                          \
   if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) \
     return launch_query_s<h, k, p, s, e, 2, 8>(a, mode, st);
+  NASG_FOR_EACH_RESIDENT_QUERY(NASG_CASE)
+#undef NASG_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t query_workgroups_per_cu(const NetDims& d, int prec, int mode, int lds_bytes, int* per_cu) {
+#define NASG_CASE(h, k, p)                                                        \
+  if (d.H == h && d.K == k && prec == p && d.E == 0)                              \
+    return d.S ? occupancy_s<h, k, p, 1, 0, 1, 4>(mode, lds_bytes, per_cu)       \
+               : occupancy_s<h, k, p, 0, 0, 1, 4>(mode, lds_bytes, per_cu);
+  NASG_FOR_EACH_NET(NASG_CASE)
+#undef NASG_CASE
+#define NASG_CASE(h, k, p, s, e)                                 \
+  if (d.H == h && d.K == k && prec == p && d.S == s && d.E == e) \
+    return occupancy_s<h, k, p, s, e, 2, 8>(mode, lds_bytes, per_cu);
   NASG_FOR_EACH_RESIDENT_QUERY(NASG_CASE)
 #undef NASG_CASE
   return hipErrorInvalidValue;

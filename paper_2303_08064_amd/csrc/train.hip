@@ -271,16 +271,11 @@ static hipError_t launch_train_s(const TrainArgs& a, int n_wg, hipStream_t st) {
   const size_t stage = sizeof(typename C::S) * C::stage_elems();
   const size_t shmem = (size_t)a.lds_bytes + stage;
   auto kern = train_kernel<H, K, PREC, SEL>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // the largest footprint of this network shape (4 hidden layers)
-    const NetDims d{H, C::NHMAX, K, SEL};
-    const size_t wmax = PREC == 1 ? (size_t)Bf16Layout{d}.total_elems() * 2 : (size_t)F32Layout{d}.total_elems() * 4;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(wmax + stage));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // the largest footprint of this network shape (4 hidden layers)
+  const NetDims d{H, C::NHMAX, K, SEL};
+  const size_t wmax = PREC == 1 ? (size_t)Bf16Layout{d}.total_elems() * 2 : (size_t)F32Layout{d}.total_elems() * 4;
+  hipError_t e = set_max_lds_once<train_kernel<H, K, PREC, SEL>>(wmax + stage);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(n_wg), dim3(64 * C::NW), shmem, st, a);
   return hipGetLastError();
 }
@@ -299,13 +294,17 @@ hipError_t launch_train(const TrainArgs& a, int H, int K, int prec, int n_wg, hi
 }
 
 // ---------------------------------------------------------------- reduce ----
-// grad[i] = sum over workgroups of partial[wg][i] in a fixed order: thread
-// group q (of 16) of a block sums workgroups q, q+16, q+32, ... for four
-// consecutive weights with 16-byte loads (all of them in flight, FP64 sums),
-// then the 16 group sums are added in order. Each block also writes its FP64
-// sum of grad^2; block 0 totals the loss partials (strided per thread, then
-// a fixed tree). n_weights is a multiple of 4 for every compiled network
-// (checked on the host); at most 256 workgroup partials, 512 loss partials.
+// grad[i] = sum over workgroups of partial[wg][i] in FP32, in a fixed
+// pairwise order: thread group q (of 16) of a block loads workgroups q, q+16,
+// q+32, ... for four consecutive weights with 16-byte loads (all of them in
+// flight) and adds them as a binary tree; the 16 group sums are then added
+// as a binary tree too. Eight levels for 256 partials: the rounding error is
+// at most 8 u times the sum of the partials' magnitudes, and the result is
+// bitwise reproducible. Each block also writes its FP64 sum of grad^2 (the
+// gradient norm of the non-finite check); block 0 totals the FP64 loss
+// partials (strided per thread, then a fixed tree). n_weights is a multiple
+// of 4 for every compiled network (checked on the host); at most 256
+// workgroup partials, 512 loss partials.
 constexpr int kRedW = 64;   // weights per block
 constexpr int kRedQ = 16;   // workgroup groups per block
 constexpr int kRedT = kMaxTrainWG / kRedQ;   // partial rows per group
@@ -313,33 +312,44 @@ constexpr int kRedT = kMaxTrainWG / kRedQ;   // partial rows per group
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const int j = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int64_t i0 = (int64_t)blockIdx.x * kRedW + 4 * j;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  float4 x[kRedT];
+#pragma unroll
+  for (int t = 0; t < kRedT; ++t) x[t] = float4{0.0f, 0.0f, 0.0f, 0.0f};
   if (i0 < a.n_weights) {
     const float* p = a.partial + i0;
-    float4 x[kRedT];
 #pragma unroll
     for (int t = 0; t < kRedT; ++t) {
       const int wg = q + kRedQ * t;
-      x[t] = wg < a.n_wg ? *reinterpret_cast<const float4*>(p + (int64_t)wg * a.n_weights)
-                         : float4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
-#pragma unroll
-    for (int t = 0; t < kRedT; ++t) {
-      s[0] += (double)x[t].x; s[1] += (double)x[t].y; s[2] += (double)x[t].z; s[3] += (double)x[t].w;
+      if (wg < a.n_wg) x[t] = *reinterpret_cast<const float4*>(p + (int64_t)wg * a.n_weights);
     }
   }
-  __shared__ double part[kRedQ][kRedW];
+#pragma unroll
+  for (int h = kRedT / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int t = 0; t < h; ++t) {
+      x[t].x += x[t + h].x;
+      x[t].y += x[t + h].y;
+      x[t].z += x[t + h].z;
+      x[t].w += x[t + h].w;
+    }
+  __shared__ float part[kRedQ][kRedW];
   __shared__ double red[256];
   __shared__ double red_w[256];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) part[q][4 * j + u] = s[u];
+  part[q][4 * j + 0] = x[0].x;
+  part[q][4 * j + 1] = x[0].y;
+  part[q][4 * j + 2] = x[0].z;
+  part[q][4 * j + 3] = x[0].w;
   __syncthreads();
   if (threadIdx.x < kRedW) {
     const int64_t i = (int64_t)blockIdx.x * kRedW + threadIdx.x;
-    double t = 0.0;
+    float g[kRedQ];
 #pragma unroll
-    for (int k = 0; k < kRedQ; ++k) t += part[k][threadIdx.x];
-    const float gf = (float)t;
+    for (int k = 0; k < kRedQ; ++k) g[k] = part[k][threadIdx.x];
+#pragma unroll
+    for (int h = kRedQ / 2; h >= 1; h >>= 1)
+#pragma unroll
+      for (int k = 0; k < h; ++k) g[k] += g[k + h];
+    const float gf = g[0];
     if (i < a.n_weights) a.grad[i] = gf;
     red[threadIdx.x] = i < a.n_weights ? (double)gf * (double)gf : 0.0;
   }
