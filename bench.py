@@ -70,10 +70,17 @@ def parse():
     return p.parse_args()
 
 
-class Frame:
-    """Device-resident inputs and the launch sequence of one frame."""
+# Frames of distinct inputs that the frame loop cycles through: 8 x 121 MB
+# of vertices and training samples, so that no frame finds its inputs in the
+# 256 MB last-level cache (a renderer streams new vertices every frame)
+SLICES = 8
 
-    def __init__(self, precision, seed=1000):
+
+class Frame:
+    """Device-resident inputs of SLICES frames and the launch sequence of one
+    frame; frame i reads slice i mod SLICES."""
+
+    def __init__(self, precision, seed=1000, n_slices=SLICES):
         import torch
         from paper_2303_08064_amd import synth
         from paper_2303_08064_amd.nasg import NasgGuide
@@ -83,21 +90,24 @@ class Frame:
                                precision=precision, lr=1e-3, max_batch=TRAIN_B)
         rng = synth.rng_for(seed)
         dev = "cuda"
-        self.q_in = []
-        for n in BOUNCES:
-            self.q_in.append((torch.from_numpy(synth.features(n, rng)).to(dev),
-                              torch.from_numpy(synth.uniforms(n, rng)).to(dev)))
-        self.q_out = [(torch.empty(3, n, device=dev), torch.empty(n, device=dev)) for n in BOUNCES]
         tgt = synth.VmfTarget(4, seed=1001)
-        f, d, w = synth.training_batch(TRAIN_B, rng, tgt)
-        self.t_in = (torch.from_numpy(f).to(dev), torch.from_numpy(d).to(dev), torch.from_numpy(w).to(dev))
+        self.slices = []
+        for _ in range(n_slices):
+            q_in = [(torch.from_numpy(synth.features(n, rng)).to(dev),
+                     torch.from_numpy(synth.uniforms(n, rng)).to(dev)) for n in BOUNCES]
+            f, d, w = synth.training_batch(TRAIN_B, rng, tgt)
+            t_in = (torch.from_numpy(f).to(dev), torch.from_numpy(d).to(dev), torch.from_numpy(w).to(dev))
+            self.slices.append((q_in, t_in))
+        self.q_in, self.t_in = self.slices[0]
+        self.q_out = [(torch.empty(3, n, device=dev), torch.empty(n, device=dev)) for n in BOUNCES]
         torch.cuda.synchronize()
 
-    def run(self):
+    def run(self, i=0):
         g = self.guide
-        for (f, xi), (d, p) in zip(self.q_in, self.q_out):
+        q_in, t_in = self.slices[i % len(self.slices)]
+        for (f, xi), (d, p) in zip(q_in, self.q_out):
             g.query(f, xi, dir_out=d, pdf_out=p)
-        g.train_step(*self.t_in)
+        g.train_step(*t_in)
 
 
 # The paper's default configuration (Sec. 4.1, Sec. 6): 4 hidden layers of
@@ -187,31 +197,38 @@ def mlp_flops_net(hidden, n_hidden, k, n_in, sel):
 
 
 def time_frames(frame, steps, warmup, use_graph):
+    """Milliseconds per frame over `steps` frames after `warmup` untimed ones.
+    With use_graph, each slice's frame is captured once as a HIP graph and the
+    graphs are replayed in turn (frame i: slice i mod the number of slices)."""
     import torch
-    for _ in range(warmup):
-        frame.run()
+    n_slices = len(getattr(frame, "slices", [None]))
+    for i in range(warmup):
+        frame.run(i) if n_slices > 1 else frame.run()
     torch.cuda.synchronize()
-    replay = frame.run
+    replays = [(lambda i=i: frame.run(i)) for i in range(n_slices)] if n_slices > 1 else [frame.run]
     if use_graph:
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
-        graph = torch.cuda.CUDAGraph()
+        graphs = []
         with torch.cuda.stream(s):
-            frame.run()   # one more eager pass on the capture stream
-            torch.cuda.synchronize()
-            with torch.cuda.graph(graph, stream=s):
-                frame.run()
+            for run in replays:
+                run()   # one more eager pass on the capture stream
+                torch.cuda.synchronize()
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph, stream=s):
+                    run()
+                graphs.append(graph)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
-        replay = graph.replay
-        for _ in range(2):
-            replay()
+        replays = [g.replay for g in graphs]
+        for r in replays:
+            r()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
-        replay()
+    for i in range(steps):
+        replays[i % len(replays)]()
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -487,7 +504,8 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    frame = Frame("bf16")
+    # the single-kernel legs read one set of inputs; the frame loop cycles through SLICES
+    frame = Frame("bf16", n_slices=SLICES if a.only in (None, "frame") else 1)
     if a.only == "query":
         ms = query_launch_ms(frame, reps=a.steps)
         print(json.dumps({"only": "query", "steps": a.steps, "avg_ms": round(ms, 4)}))
@@ -546,7 +564,8 @@ def main():
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "online guiding frame loop: NASG MLP 9->64x4->8*16 (K=16), queries "
                                "2^20+600000+300000+120000 (fwd+sample+pdf) and one 2^18-sample training "
-                               "step (fwd+bwd+Adam) per frame, HIP graph replay",
+                               "step (fwd+bwd+Adam) per frame, HIP graph replay; frames cycle through "
+                               f"{SLICES} sets of distinct inputs ({SLICES} x 121 MB, past the last-level cache)",
                    "queries_per_frame": nq, "train_samples_per_frame": TRAIN_B,
                    "hidden": H, "n_hidden": NH, "n_lobes": K, "precision": "bf16"},
         "train_samples_per_s": round(TRAIN_B / (ms * 1e-3), 1),
