@@ -472,3 +472,32 @@ def test_isotropic_query_and_gradient(name):
     assert max(errs) < (1e-4 if prec == "f32" else 2e-2), errs
     a_rows = [6 * K + k for k in range(K)]   # canonical rows of the log a outputs
     assert float(torch.abs(gg[-1][a_rows]).max()) == 0.0
+
+
+@pytest.mark.parametrize("name", ["c1_bf16", "c3_bf16", "c3s_bf16", "c2_bf16", "c3_f32", "paper_bf16"])
+def test_query_batch_invariance(name):
+    """Each vertex's query is computed from that vertex alone, so a ragged or
+    tiny batch must give, bit for bit, what the same vertices give inside a
+    larger batch: this pins the kernels' vertex indexing, tail masks and
+    lane exchanges (the hidden-64 BF16 networks sample one vertex per lane
+    over four 16-vertex blocks) for batches that end inside a block, inside a
+    pass and inside a tile."""
+    K = CONFIGS[name][2]
+    g, _ = make_guide(name)
+    full = 4096
+    feat, xi = inputs(full, 11)
+    sel_net = g.selection
+    fd, xd = to_dev(feat), to_dev(xi)
+    ref_sel = torch.empty(full, device="cuda") if sel_net else None
+    d0, p0, r0 = g.query(fd, xd, records=True, sel_out=ref_sel)
+    torch.cuda.synchronize()
+    for B in (1, 15, 17, 63, 65, 129, 1000):
+        f, x = to_dev(np.ascontiguousarray(feat[:, :B])), to_dev(np.ascontiguousarray(xi[:, :B]))
+        sel = torch.empty(B, device="cuda") if sel_net else None
+        d, p, r = g.query(f, x, records=True, sel_out=sel)
+        torch.cuda.synchronize()
+        assert torch.equal(d, d0[:, :B]) and torch.equal(p, p0[:B]), (name, B)
+        assert np.array_equal(rec_to_bk9(r, B, K), rec_to_bk9(r0, full, K)[:B]), (name, B)
+        if sel_net:
+            assert torch.equal(sel, ref_sel[:B]), (name, B)
+    g.close()
