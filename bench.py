@@ -118,9 +118,10 @@ PAPER_T, PAPER_TB = 16, 4096
 
 class PaperFrame:
     """One frame of the paper's default configuration: the same four bounces
-    of queries, then T Adam steps of t samples each on the blended loss."""
+    of queries, then T Adam steps of t samples each on the blended loss;
+    frame i reads the i mod n_slices-th set of inputs, as in Frame."""
 
-    def __init__(self, seed=3000, precision="bf16"):
+    def __init__(self, seed=3000, precision="bf16", n_slices=SLICES):
         import torch
         from paper_2303_08064_amd import synth
         from paper_2303_08064_amd.nasg import NasgGuide
@@ -130,23 +131,28 @@ class PaperFrame:
                                lr=1e-3, max_batch=PAPER_TB, selection=True, mis_fraction=0.2, encoded=True)
         rng = synth.rng_for(seed)
         dev = "cuda"
-        self.q_in = [(torch.from_numpy(synth.features(n, rng)).to(dev),
-                      torch.from_numpy(synth.uniforms(n, rng)).to(dev)) for n in BOUNCES]
+        tgt = synth.VmfTarget(4, seed=1001)
+        self.slices = []
+        for _ in range(n_slices):
+            q_in = [(torch.from_numpy(synth.features(n, rng)).to(dev),
+                     torch.from_numpy(synth.uniforms(n, rng)).to(dev)) for n in BOUNCES]
+            t_in = []
+            for _ in range(PAPER_T):
+                f, d, w = synth.training_batch(PAPER_TB, rng, tgt)
+                pdf = synth.lambert_pdf(d, f[6:9])
+                t_in.append(tuple(torch.from_numpy(x).to(dev) for x in (f, d, w, pdf)))
+            self.slices.append((q_in, t_in))
+        self.q_in, self.t_in = self.slices[0]
         self.q_out = [(torch.empty(3, n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev))
                       for n in BOUNCES]
-        tgt = synth.VmfTarget(4, seed=1001)
-        self.t_in = []
-        for _ in range(PAPER_T):
-            f, d, w = synth.training_batch(PAPER_TB, rng, tgt)
-            pdf = synth.lambert_pdf(d, f[6:9])
-            self.t_in.append(tuple(torch.from_numpy(x).to(dev) for x in (f, d, w, pdf)))
         torch.cuda.synchronize()
 
-    def run(self):
+    def run(self, i=0):
         g = self.guide
-        for (f, xi), (d, p, c) in zip(self.q_in, self.q_out):
+        q_in, t_in = self.slices[i % len(self.slices)]
+        for (f, xi), (d, p, c) in zip(q_in, self.q_out):
             g.query(f, xi, dir_out=d, pdf_out=p, sel_out=c)
-        for f, d, w, pdf in self.t_in:
+        for f, d, w, pdf in t_in:
             g.train_step(f, d, w, bsdf_pdf=pdf)
 
 
@@ -179,7 +185,8 @@ def paper_leg(steps, use_graph, fp32=True):
     return {
         "workload": "paper default: encoded input (one-blob 57 + omega_o + n + 1 = 64) -> 128x4 -> 8*8+1 "
                     "(K=8 with selection), BF16; queries 2^20+600000+300000+120000 and 16 Adam steps of "
-                    "4096 samples (S = 2^16, blended loss) per frame, HIP graph replay",
+                    f"4096 samples (S = 2^16, blended loss) per frame, HIP graph replay; frames cycle through "
+                    f"{SLICES} sets of distinct inputs",
         "ms_per_frame": round(ms, 4), "queries_per_s": round(nq / (ms * 1e-3), 1),
         "train_samples_per_s": round(ns / (ms * 1e-3), 1),
         "query_2e20_ms": round(ms_q, 4), "query_mfma_tflops": round(q_fl * (1 << 20) / (ms_q * 1e-3) / 1e12, 1),
@@ -533,7 +540,7 @@ def main():
         print(json.dumps({"only": "c5", "steps": a.steps, "ms_per_step": round(ms, 4)}))
         return
     if a.only in ("paper_query", "paper_train"):
-        fr = PaperFrame()
+        fr = PaperFrame(n_slices=1)
         (f, xi), (d, p, c) = fr.q_in[0], fr.q_out[0]
         for _ in range(a.steps):
             if a.only == "paper_query":
