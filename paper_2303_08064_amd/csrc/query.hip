@@ -21,6 +21,11 @@ namespace nasg {
 // network two, its 132 KiB of forward weights leaving room for one
 // workgroup per CU.
 constexpr bool query_four(int H, int K, int MODE, int PREC) { return H == 64 && K != 8 && MODE == 0 && PREC == 1; }
+// dynamic LDS of a query launch: the weights, plus the four-block kernels'
+// two input staging buffers per wave
+constexpr size_t query_dynamic_lds(int weight_bytes, bool four, int nw) {
+  return (size_t)weight_bytes + (four ? (size_t)nw * 2 * (kInFeatures + 4) * 64 * sizeof(float) : 0);
+}
 constexpr int query_waves_per_eu(int H, int K, int MODE, int PREC) {
   return H == 64 ? (MODE == 0 ? (query_four(H, K, MODE, PREC) ? 2 : 3) : 1) : 2;
 }
@@ -81,6 +86,45 @@ __device__ __forceinline__ void store_records(const QueryArgs& a, const Lobe (&l
   }
 }
 
+// Inputs of one 64-vertex pass staged in LDS: the 9 feature rows and the 4
+// uniform rows, 64 floats each (lane i of a row = vertex 64 tile + i).
+constexpr int kPassRows = kInFeatures + 4;
+constexpr int kPassStage = kPassRows * 64;   // floats per wave and buffer
+
+// Direct-to-LDS copies of a pass's inputs (13 wave instructions, no
+// registers). Lanes past the batch read vertex B - 1 instead (in bounds;
+// their values are never used), so that every wave issues the same number of
+// copies and s_waitcnt can count them.
+__device__ __forceinline__ void stage_pass(const QueryArgs& a, int64_t tile, float* buf, int lane) {
+  int64_t v = tile * (4 * kTileV) + lane;
+  v = v < a.B ? v : a.B - 1;
+#pragma unroll
+  for (int k = 0; k < kInFeatures; ++k)
+    __builtin_amdgcn_global_load_lds(a.feat + k * a.ld + v, (__attribute__((address_space(3))) void*)(buf + k * 64), 4,
+                                     0, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    __builtin_amdgcn_global_load_lds(a.xi + k * a.ld + v,
+                                     (__attribute__((address_space(3))) void*)(buf + (kInFeatures + k) * 64), 4, 0, 0);
+}
+
+// Layer 0's input of vertex `col` of a staged pass (as the Mlp's load_raw:
+// features 4g .. 4g + 3 of the 9, then the constant one, then zeros)
+__device__ __forceinline__ bf16x4 staged_input(const float* buf, int col, bool valid, int g) {
+  float f[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 4 * g + j;
+    float x = 0.0f;
+    if (valid) {
+      if (k < kInFeatures) x = buf[k * 64 + col];
+      else if (k == kInFeatures) x = 1.0f;
+    }
+    f[j] = x;
+  }
+  return bf16x4{(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
+}
+
 // The query (MODE 0) of the hidden-64 networks, one sample per lane: a wave
 // takes four 16-vertex blocks per pass. For each block it runs the forward,
 // decodes the lobes (lane (g, c): vertex c, lobes g*K/4 ..), chooses a lobe
@@ -92,9 +136,9 @@ __device__ __forceinline__ void store_records(const QueryArgs& a, const Lobe (&l
 // same order as the one-block pass, so the same results bit for bit.
 template <int H, int K, int PREC, int S, int E, int NW>
 __device__ __forceinline__ void query_four_blocks(const QueryArgs& a, const typename Forward<H, K, PREC, 4, S, E>::W* wts,
-                                                  int64_t tile, int lane) {
-  typedef Mlp<H, K, PREC, E> M;
+                                                  int64_t tile, const float* in, int lane) {
   typedef Forward<H, K, PREC, 4, S, E> F;
+  static_assert(E == 0, "staged raw features");
   constexpr int KQ = K / 4;
   constexpr int MTO = F::MTO;
   const int g = lane >> 4, c = lane & 15;
@@ -104,12 +148,12 @@ __device__ __forceinline__ void query_four_blocks(const QueryArgs& a, const type
   for (int b = 0; b < 4; ++b) {
     const int64_t v = tile * (4 * kTileV) + b * kTileV + c;
     const bool valid = v < a.B;
-    typename M::Input x = M::load_input(a.feat, a.ld, v, valid, g);
+    const bf16x4 x = staged_input(in, b * kTileV + c, valid, g);
     float out[MTO][4];
     F::run_query(wts, a.nh, x, out, lane);
     float A[KQ];
     query_decode<KQ, MTO>(out, a.eps, lb[b], A, a.amul);
-    const float xs = valid ? a.xi[v] : 0.0f;
+    const float xs = valid ? in[kInFeatures * 64 + b * kTileV + c] : 0.0f;
     const int k = select_lobe<KQ>(A, xs, g, c);
     const Lobe r = broadcast_lobe<KQ>(lb[b], k, c);
     if (g == b) ch = r;
@@ -119,12 +163,9 @@ __device__ __forceinline__ void query_four_blocks(const QueryArgs& a, const type
   }
   const int64_t vm = tile * (4 * kTileV) + lane;   // vertex (block g, c)
   const bool mine = vm < a.B;
-  float xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
-  if (mine) {
-    xi0 = a.xi[a.ld + vm];
-    xi1 = a.xi[2 * a.ld + vm];
-    xi2 = a.xi[3 * a.ld + vm];
-  }
+  const float xi0 = mine ? in[(kInFeatures + 1) * 64 + lane] : 0.0f;
+  const float xi1 = mine ? in[(kInFeatures + 2) * 64 + lane] : 0.0f;
+  const float xi2 = mine ? in[(kInFeatures + 3) * 64 + lane] : 0.0f;
   float vx, vy, vz;
   sample_unit(ch, xi0, xi1, xi2, a.eps, vx, vy, vz);
   float logq = 0.0f;
@@ -168,9 +209,25 @@ void query_kernel(QueryArgs a) {
   const int g = lane >> 4, c = lane & 15;
   const int wave = threadIdx.x >> 6;
   if constexpr (query_four(H, K, MODE, PREC)) {
+    // each wave's two staging buffers follow the weights: the next pass's
+    // inputs are copied while this pass runs, so no block waits for memory
+    float* stage = reinterpret_cast<float*>(smem + a.lds_bytes) + wave * 2 * kPassStage;
     const int64_t n_tiles = (a.B + 4 * kTileV - 1) / (4 * kTileV);
-    for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += (int64_t)gridDim.x * NW)
-      query_four_blocks<H, K, PREC, S, E, NW>(a, wts, tile, lane);
+    const int64_t stride = (int64_t)gridDim.x * NW;
+    int64_t tile = (int64_t)blockIdx.x * NW + wave;
+    if (tile < n_tiles) stage_pass(a, tile, stage, lane);
+    for (int p = 0; tile < n_tiles; tile += stride, p ^= 1) {
+      float* cur = stage + p * kPassStage;
+      if (tile + stride < n_tiles) {
+        stage_pass(a, tile + stride, stage + (p ^ 1) * kPassStage, lane);
+        // the current pass's 13 copies and everything before them are done;
+        // the 13 just issued may still be in flight
+        __builtin_amdgcn_s_waitcnt(0x0F70 | 13);
+      } else {
+        lds_dma_wait();
+      }
+      query_four_blocks<H, K, PREC, S, E, NW>(a, wts, tile, cur, lane);
+    }
     return;
   }
   constexpr int TV = kTileV * NB;   // vertices per wave pass
@@ -200,13 +257,14 @@ void query_kernel(QueryArgs a) {
 template <int H, int K, int PREC, int S, int E, int NB, int NW>
 static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
   auto kern = mode == 0 ? query_kernel<H, K, PREC, 0, S, E, NB, NW> : query_kernel<H, K, PREC, 1, S, E, NB, NW>;
-  const int TV = kTileV * (query_four(H, K, mode, PREC) ? 4 : NB);   // vertices per wave pass
+  const bool four = query_four(H, K, mode, PREC);
+  const int TV = kTileV * (four ? 4 : NB);   // vertices per wave pass
   const int64_t n_tiles = (a.B + TV - 1) / TV;
   const int64_t want = (n_tiles + NW - 1) / NW;
   const int64_t cap = (int64_t)(a.per_cu < 1 ? 1 : a.per_cu) * a.num_cus;
   int grid = (int)(want < cap ? want : cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), a.lds_bytes, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), query_dynamic_lds(a.lds_bytes, four, NW), st, a);
   return hipGetLastError();
 }
 
@@ -216,8 +274,11 @@ static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
 template <int H, int K, int PREC, int S, int E, int NB, int NW>
 static hipError_t occupancy_s(int mode, int lds_bytes, int* per_cu) {
   const NetDims dmax{H, 4, K, S, E};
-  const int max_bytes = PREC == 1 ? (int)Bf16Layout{dmax}.fwd_elems() * 2 : (int)F32Layout{dmax}.total_elems() * 4;
-  if (lds_bytes > max_bytes) return hipErrorInvalidValue;
+  const int max_w = PREC == 1 ? (int)Bf16Layout{dmax}.fwd_elems() * 2 : (int)F32Layout{dmax}.total_elems() * 4;
+  if (lds_bytes > max_w) return hipErrorInvalidValue;
+  const bool four = query_four(H, K, mode, PREC);
+  const int max_bytes = (int)query_dynamic_lds(max_w, four, NW);
+  lds_bytes = (int)query_dynamic_lds(lds_bytes, four, NW);
   hipError_t e = mode == 0 ? set_max_lds_once<query_kernel<H, K, PREC, 0, S, E, NB, NW>>(max_bytes)
                            : set_max_lds_once<query_kernel<H, K, PREC, 1, S, E, NB, NW>>(max_bytes);
   if (e != hipSuccess) return e;
