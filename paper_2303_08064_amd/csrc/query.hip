@@ -23,8 +23,10 @@ namespace nasg {
 constexpr bool query_four(int H, int K, int MODE, int PREC) { return H == 64 && K != 8 && MODE == 0 && PREC == 1; }
 // dynamic LDS of a query launch: the weights, plus the four-block kernels'
 // two input staging buffers per wave
-constexpr size_t query_dynamic_lds(int weight_bytes, bool four, int nw) {
-  return (size_t)weight_bytes + (four ? (size_t)nw * 2 * (kInFeatures + 4) * 64 * sizeof(float) : 0);
+constexpr size_t query_dynamic_lds(int weight_bytes, bool four, int nb, int nw) {
+  return (size_t)weight_bytes +
+         (four ? (size_t)nw * 2 * (kInFeatures + 4) * 64 * sizeof(float)
+               : (nb == 2 ? (size_t)nw * 2 * (kInFeatures + 4) * 32 * sizeof(float) : 0));
 }
 constexpr int query_waves_per_eu(int H, int K, int MODE, int PREC) {
   return H == 64 ? (MODE == 0 ? (query_four(H, K, MODE, PREC) ? 2 : 3) : 1) : 2;
@@ -35,7 +37,7 @@ constexpr int query_waves_per_eu(int H, int K, int MODE, int PREC) {
 // raw outputs in canonical row order (MODE 1).
 template <int K, int MODE, int S, int MTO>
 __device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&out)[MTO][4], int64_t v, int g,
-                                             int c) {
+                                             int c, const float* xi, int64_t xi_ld, int64_t xi_col) {
   constexpr int KQ = K / 4;
   const bool valid = v < a.B;
   if (MODE == 1) {
@@ -52,10 +54,10 @@ __device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&o
   }
   float xi_sel = 0.0f, xi0 = 0.0f, xi1 = 0.0f, xi2 = 0.0f;
   if (valid) {
-    xi_sel = a.xi[v];
-    xi0 = a.xi[a.ld + v];
-    xi1 = a.xi[2 * a.ld + v];
-    xi2 = a.xi[3 * a.ld + v];
+    xi_sel = xi[xi_col];
+    xi0 = xi[xi_ld + xi_col];
+    xi1 = xi[2 * xi_ld + xi_col];
+    xi2 = xi[3 * xi_ld + xi_col];
   }
   Lobe lb[KQ];
   float vx, vy, vz;
@@ -106,6 +108,24 @@ __device__ __forceinline__ void stage_pass(const QueryArgs& a, int64_t tile, flo
   for (int k = 0; k < 4; ++k)
     __builtin_amdgcn_global_load_lds(a.xi + k * a.ld + v,
                                      (__attribute__((address_space(3))) void*)(buf + (kInFeatures + k) * 64), 4, 0, 0);
+}
+
+// The same for a 32-vertex pass (two 16-vertex blocks): each copy moves two
+// rows, lanes 0-31 the first and 32-63 the second (lanes past the last row
+// copy nothing); the uniforms only for a query (XI). ceil(rows / 2) copies.
+template <bool XI>
+__device__ __forceinline__ void stage_pass32(const QueryArgs& a, int64_t tile, float* buf, int lane) {
+  constexpr int rows = kInFeatures + (XI ? 4 : 0);
+  int64_t v = tile * (2 * kTileV) + (lane & 31);
+  v = v < a.B ? v : a.B - 1;
+#pragma unroll
+  for (int j = 0; j < (rows + 1) / 2; ++j) {
+    const int r = 2 * j + (lane >> 5);
+    if (r < rows) {
+      const float* src = r < kInFeatures ? a.feat + r * a.ld + v : a.xi + (r - kInFeatures) * a.ld + v;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(buf + 2 * j * 32), 4, 0, 0);
+    }
+  }
 }
 
 // Layer 0's input of vertex `col` of a staged pass (as the Mlp's load_raw:
@@ -232,24 +252,44 @@ void query_kernel(QueryArgs a) {
   }
   constexpr int TV = kTileV * NB;   // vertices per wave pass
   const int64_t n_tiles = (a.B + TV - 1) / TV;
-  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += (int64_t)gridDim.x * NW) {
-    if constexpr (NB == 1) {
+  const int64_t stride = (int64_t)gridDim.x * NW;
+  if constexpr (NB == 1) {
+    for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < n_tiles; tile += stride) {
       const int64_t v = tile * kTileV + c;
       typename M::Input x = M::load_input(a.feat, a.ld, v, v < a.B, g);
       float out[F::MTO][4];
       F::run_query(wts, a.nh, x, out, lane);
-      finish_block<K, MODE, S>(a, out, v, g, c);
-    } else {
+      finish_block<K, MODE, S>(a, out, v, g, c, a.xi, a.ld, v);
+    }
+  } else {
+    // two 16-vertex blocks per pass, their inputs staged in LDS one pass
+    // ahead (as in query_four_blocks): the rows of a pass are [row][32]
+    static_assert(NB == 2, "32-vertex passes");
+    constexpr int ROWS = kInFeatures + (MODE == 0 ? 4 : 0);
+    constexpr int COPIES = (ROWS + 1) / 2;
+    float* stage = reinterpret_cast<float*>(smem + a.lds_bytes) + wave * 2 * (kPassRows * 32);
+    int64_t tile = (int64_t)blockIdx.x * NW + wave;
+    if (tile < n_tiles) stage_pass32<MODE == 0>(a, tile, stage, lane);
+    for (int p = 0; tile < n_tiles; tile += stride, p ^= 1) {
+      const float* cur = stage + p * (kPassRows * 32);
+      if (tile + stride < n_tiles) {
+        stage_pass32<MODE == 0>(a, tile + stride, stage + (p ^ 1) * (kPassRows * 32), lane);
+        __builtin_amdgcn_s_waitcnt(0x0F70 | COPIES);
+      } else {
+        lds_dma_wait();
+      }
       typename M::Input x[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int64_t v = tile * TV + nb * kTileV + c;
-        x[nb] = M::load_input(a.feat, a.ld, v, v < a.B, g);
+        x[nb] = M::load_input(cur, 32, nb * kTileV + c, v < a.B, g);
       }
       float out[NB][F::MTO][4];
       F::template run_query_nb<NB, MODE == 0>(wts, a.nh, x, out, lane);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) finish_block<K, MODE, S>(a, out[nb], tile * TV + nb * kTileV + c, g, c);
+      for (int nb = 0; nb < NB; ++nb)
+        finish_block<K, MODE, S>(a, out[nb], tile * TV + nb * kTileV + c, g, c, cur + kInFeatures * 32, 32,
+                                 nb * kTileV + c);
     }
   }
 }
@@ -264,7 +304,7 @@ static hipError_t launch_query_s(const QueryArgs& a, int mode, hipStream_t st) {
   const int64_t cap = (int64_t)(a.per_cu < 1 ? 1 : a.per_cu) * a.num_cus;
   int grid = (int)(want < cap ? want : cap);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), query_dynamic_lds(a.lds_bytes, four, NW), st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), query_dynamic_lds(a.lds_bytes, four, NB, NW), st, a);
   return hipGetLastError();
 }
 
@@ -277,8 +317,8 @@ static hipError_t occupancy_s(int mode, int lds_bytes, int* per_cu) {
   const int max_w = PREC == 1 ? (int)Bf16Layout{dmax}.fwd_elems() * 2 : (int)F32Layout{dmax}.total_elems() * 4;
   if (lds_bytes > max_w) return hipErrorInvalidValue;
   const bool four = query_four(H, K, mode, PREC);
-  const int max_bytes = (int)query_dynamic_lds(max_w, four, NW);
-  lds_bytes = (int)query_dynamic_lds(lds_bytes, four, NW);
+  const int max_bytes = (int)query_dynamic_lds(max_w, four, NB, NW);
+  lds_bytes = (int)query_dynamic_lds(lds_bytes, four, NB, NW);
   hipError_t e = mode == 0 ? set_max_lds_once<query_kernel<H, K, PREC, 0, S, E, NB, NW>>(max_bytes)
                            : set_max_lds_once<query_kernel<H, K, PREC, 1, S, E, NB, NW>>(max_bytes);
   if (e != hipSuccess) return e;
