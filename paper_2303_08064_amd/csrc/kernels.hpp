@@ -43,7 +43,7 @@ struct QueryArgs {
   int sel;               // 1: the network has the selection output (8K + 1 rows)
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
-  int per_cu;            // resident query kernel: workgroups per CU at this LDS footprint
+  int per_cu = 1;        // resident query kernel: workgroups per CU at this LDS footprint
 };
 
 struct RecArgs {
@@ -92,7 +92,7 @@ struct LargeTrainArgs {
   int64_t n_weights;
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
-  int per_cu;            // resident query kernel: workgroups per CU at this LDS footprint
+  int per_cu = 1;        // resident query kernel: workgroups per CU at this LDS footprint
 };
 
 struct ReduceArgs {
