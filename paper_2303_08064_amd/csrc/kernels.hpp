@@ -92,7 +92,6 @@ struct LargeTrainArgs {
   int64_t n_weights;
   float amul;            // 1: NASG lobes; 0: isotropic lobes (a = 0)
   int num_cus;
-  int per_cu = 1;        // resident query kernel: workgroups per CU at this LDS footprint
 };
 
 struct ReduceArgs {
