@@ -500,4 +500,9 @@ def test_query_batch_invariance(name):
         assert np.array_equal(rec_to_bk9(r, B, K), rec_to_bk9(r0, full, K)[:B]), (name, B)
         if sel_net:
             assert torch.equal(sel, ref_sel[:B]), (name, B)
+        # the same vertices as views of the full arrays: leading dimension
+        # 4096 > B (rows of the inputs and outputs 4096 floats apart)
+        dv, pv = g.query(fd[:, :B], xd[:, :B])
+        torch.cuda.synchronize()
+        assert dv.stride(0) == full and torch.equal(dv, d0[:, :B]) and torch.equal(pv, p0[:B]), (name, B)
     g.close()
