@@ -1,10 +1,13 @@
 // Fused guiding query: MLP forward on MFMA (weights LDS-resident), NASG
 // decode, inverse-CDF lobe choice, direct sampling (App. C) and the mixture
-// pdf at the sampled direction (Sec. 3.1), one wave per 16 vertices.
+// pdf at the sampled direction (Sec. 3.1), in 16-vertex blocks.
 //
-// Lane (g, c) of a wave owns vertex c of its 16-vertex block and lobes
+// Lane (g, c) of a wave owns vertex c of a 16-vertex block and lobes
 // g*K/4 .. g*K/4 + K/4 - 1 of that vertex, so reductions over lobes are a
-// within-lane loop plus two cross-lane steps (xor 16, xor 32).
+// within-lane loop plus two cross-lane steps (xor 16, xor 32). A wave takes
+// one block per pass, four (one sample per lane: query_four_blocks) or two
+// (the paper's network), with the multi-block passes' inputs staged in LDS
+// one pass ahead.
 #include <type_traits>
 
 #include "epilogue.hpp"
@@ -30,6 +33,20 @@ constexpr size_t query_dynamic_lds(int weight_bytes, bool four, int nb, int nw) 
 }
 constexpr int query_waves_per_eu(int H, int K, int MODE, int PREC) {
   return H == 64 ? (MODE == 0 ? (query_four(H, K, MODE, PREC) ? 2 : 3) : 1) : 2;
+}
+
+// Records of one 16-vertex block's lobes (optional output of a query).
+template <int KQ>
+__device__ __forceinline__ void store_records(const QueryArgs& a, const Lobe (&lb)[KQ], int64_t v, int g) {
+  constexpr int K = 4 * KQ;
+  float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int k = g * KQ + q;
+    const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz, lb[q].lam, lb[q].a, lb[q].logc};
+#pragma unroll
+    for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
+  }
 }
 
 // The rest of a query for one 16-vertex block from its raw outputs: decode,
@@ -72,20 +89,6 @@ __device__ __forceinline__ void finish_block(const QueryArgs& a, const float (&o
     if (S == 1 && a.sel_out != nullptr) a.sel_out[v] = frcp(1.0f + fexp(-out[MTO - 1][0]));
   }
   if (a.rec_out != nullptr && valid) store_records<KQ>(a, lb, v, g);
-}
-
-// Records of one 16-vertex block's lobes (optional output of a query).
-template <int KQ>
-__device__ __forceinline__ void store_records(const QueryArgs& a, const Lobe (&lb)[KQ], int64_t v, int g) {
-  constexpr int K = 4 * KQ;
-  float* base = a.rec_out + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
-#pragma unroll
-  for (int q = 0; q < KQ; ++q) {
-    const int k = g * KQ + q;
-    const float vals[9] = {lb[q].zx, lb[q].zy, lb[q].zz, lb[q].xx, lb[q].xy, lb[q].xz, lb[q].lam, lb[q].a, lb[q].logc};
-#pragma unroll
-    for (int p = 0; p < 9; ++p) base[(p * K + k) * kRecTile] = vals[p];
-  }
 }
 
 // Inputs of one 64-vertex pass staged in LDS: the 9 feature rows and the 4
