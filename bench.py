@@ -5,8 +5,9 @@ One step = one frame of a 1-spp path tracer's guiding work: NASG queries
 vertices (four bounces), then one training step (fused forward recompute +
 weighted-NLL backward + Adam) on 2^18 samples, with the BF16 network
 9 -> 64 x 4 -> 8*16 (K = 16 NASG lobes). Inputs are synthetic, seeded and
-resident in HBM before timing. The frame is captured once as a HIP graph and
-replayed. Prints one JSON line.
+resident in HBM before timing; the frames cycle through 8 sets of distinct
+inputs (8 x 121 MB, more than the last-level cache holds), each set's frame
+captured once as a HIP graph and replayed in turn. Prints one JSON line.
 
 Also measured: the same frame with the FP32 network, the stand-alone
 nasg_pdf / nasg_sample kernels on stored records (2^20 vertices), the query
