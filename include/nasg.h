@@ -108,9 +108,11 @@ size_t nasg_num_weights(const nasg_config* cfg);
 size_t nasg_packed_bytes(const nasg_config* cfg);
 size_t nasg_workspace_bytes(const nasg_config* cfg);
 
-/* Validate cfg and state, bind them to a new host-side context, and pack
- * state->w into state->wpack and clear the workspace counters on the default
- * stream (synchronised before returning). The context is not thread-safe. */
+/* Validate cfg and state, bind them to a new host-side context on the
+ * current device, and pack state->w into state->wpack on the default stream
+ * (synchronised before returning). It also looks up, once per device, the
+ * device address of nasg_train_step_noalloc's scratch array. The workspace
+ * needs no initialisation. The context is not thread-safe. */
 nasg_status nasg_create(const nasg_config* cfg, const nasg_state* state, nasg_ctx** out);
 void nasg_destroy(nasg_ctx* ctx);
 const char* nasg_last_error(void);
