@@ -70,7 +70,8 @@ typedef struct {
   int32_t selection;   /* 1: one more output, the selection probability c = sigmoid(o[8K])
                           (Sec. 4.1, Tab. "decoding"), and training on the blended loss
                           e KL(p||q_hat) + (1-e) KL(p||q), q_hat = c q + (1-c) p_fs
-                          (Sec. 4.2); hidden-64 networks only. 0: 8K outputs, NLL of q. */
+                          (Sec. 4.2); the hidden-64 networks and the paper's default network.
+                          0: 8K outputs, NLL of q. */
   float mis_fraction;  /* e of the blended loss, in [0, 1] (the paper uses 0.2) */
   int32_t isotropic;   /* 1: isotropic lobes, a = 0 (normalised spherical Gaussians / vMF, the
                           comparison model of Sec. 6); the a outputs are ignored and get zero
