@@ -32,7 +32,9 @@ the magnitude of the terms, not with the sum. Each entry is held to
   vertex may be present or not), and, for BF16 networks, a hidden
   activation or a delta that close to a bfloat16 rounding tie (one
   bfloat16 unit either way; for the raw-output delta, within 256 u of
-  itself plus its spread; for the paper network's encoded input, within
+  itself, or for a mixture logit of the two terms its gradient is the
+  difference of if that is more (``raw_grad_rounding``), plus its spread; for
+  the paper network's encoded input, within
   256 u of itself, the error of its float32 exp2). The terms such a decision can move, with
   everything they feed below, are added in absolute value.
 """
@@ -41,6 +43,7 @@ import numpy as np
 import torch
 
 from oracle import mlp as omlp
+from oracle import nasg as onasg
 from oracle import train as otrain
 
 F64 = torch.float64
@@ -55,6 +58,35 @@ ENC_SLACK = 256 * U
 # emulation (107 of 2.56 million, over four layers) lay within 0.38 u mag of
 # its tie; ten times that
 SUM = 4 * U
+
+
+def raw_grad_rounding(raw, dirs, w, K, bsdf=None, e=0.2, eps=0.0, isotropic=False):
+    """[B, n_out]: how far the kernel's float32 raw-output gradient can lie
+    from the float64 one where 256 u of the gradient itself is too narrow a
+    band, because the gradient is a difference. The gradient of lobe
+    k's logit is dL/dlog q (r_k - A_k) (Sec. 4.2 with the softmax of Tab.
+    "decoding"): the responsibility r_k = A_k G_k / (K_k q) less the mixture
+    weight A_k, two float32 values; where one lobe holds nearly all the
+    weight both are near 1 and the difference is exact only to units of
+    their sum. So 256 u |dL/dlog q| (r_k + A_k) for a logit, 0 for the other
+    outputs (products of r_k and a partial of the lobe, which the 256 u band
+    covers: r_k comes from log-domain terms a few tens in size, each rounded
+    to float32) and for the selection logit."""
+    raw = torch.as_tensor(raw, dtype=F64)
+    B = raw.shape[0]
+    lobes = onasg.decode(raw, K, eps, isotropic)
+    terms = onasg.component_log_terms(dirs, lobes)              # log(A_k G_k / K_k)
+    r = torch.exp(terms - torch.logsumexp(terms, dim=-1, keepdim=True))
+    A = torch.exp(lobes.log_A)
+    gq = torch.as_tensor(w, dtype=F64) / B                        # |dL/dlog q| of the mean NLL
+    if bsdf is not None:
+        c = onasg.selection(raw, K)
+        q = torch.exp(torch.logsumexp(terms, dim=-1))
+        qh = otrain.mis_pdf(q, c, torch.as_tensor(bsdf, dtype=F64))
+        gq = gq * (e * c * q / qh + (1.0 - e))
+    out = torch.zeros(raw.shape, dtype=F64)
+    out[:, 7 * K:8 * K] = gq.abs()[:, None] * (r + A)
+    return 256 * U * out
 
 
 def raw_grad(raw, dirs, w, K, bsdf=None, e=0.2, eps=0.0, isotropic=False):
@@ -99,13 +131,14 @@ def _bf16(t):
     return omlp.round_bf16(torch.as_tensor(t, dtype=F64).to(torch.float32).to(F64)).detach()
 
 
-def flip_allowance(W, feat, g_raw, bf16=False, raw_grad_slack=None):
+def flip_allowance(W, feat, g_raw, bf16=False, raw_grad_slack=None, raw_grad_round=None):
     """[F_l]: per weight, the sum of the magnitudes of the terms that a
     rounding-dependent decision can change (see the module docstring):
     activations that may differ (``forward_uncertainty``: bfloat16 ties,
     ambiguous ReLUs, with what the layers below pass up) times |delta|;
     deltas that may differ -- the raw-output delta near a bfloat16 tie
-    (within 256 u of itself plus raw_grad_slack, its spread), a delta whose
+    (within raw_grad_slack, its spread, plus the larger of 256 u of itself
+    and raw_grad_round, ``raw_grad_rounding``), a delta whose
     ReLU may go either way, a bfloat16 delta near a tie -- times |h|, each
     carried down through |W| to the layers below."""
     layers, Wb = forward_uncertainty(W, feat, bf16)
@@ -113,7 +146,10 @@ def flip_allowance(W, feat, g_raw, bf16=False, raw_grad_slack=None):
     d = torch.as_tensor(g_raw, dtype=F64)
     dd = torch.zeros_like(d)                     # possible change of each delta
     if bf16:
-        slack = 256 * U * d.abs() + (0 if raw_grad_slack is None else raw_grad_slack)
+        slack = 256 * U * d.abs()
+        if raw_grad_round is not None:
+            slack = torch.maximum(slack, raw_grad_round)
+        slack = slack + (0 if raw_grad_slack is None else raw_grad_slack)
         tie, ulp = _near_bf16_tie(d, slack)
         dd = tie * ulp
         d = _bf16(d)                             # the delta the emulation multiplies with
@@ -255,7 +291,7 @@ def tolerance(W, feat, raw, dirs, w, K, scale, bf16=False, n_random=8, seed=0, *
         gp = otrain.weight_grad_from_raw_grad(W, feat, gr, bf16=bf16)
         spread = [torch.maximum(s, (a - b).abs()) for s, a, b in zip(spread, gp, ref)]
     S = term_magnitudes(W, feat, g_raw)
-    Fl = flip_allowance(W, feat, g_raw, bf16, graw_spread)
+    Fl = flip_allowance(W, feat, g_raw, bf16, graw_spread, raw_grad_rounding(raw, dirs, w, K, **kw) if bf16 else None)
     tol = [1e-4 * g.abs() + 1e-7 * g.abs().max() + s + 32 * U * m + f for g, s, m, f in zip(ref, spread, S, Fl)]
     return ref, tol
 
