@@ -139,17 +139,38 @@ __device__ __forceinline__ int select_lobe(const float (&A)[KQ], float xi, int g
   float P = g == 0 ? 0.0f : (g == 1 ? t0 : (g == 2 ? p01 : p012));
   float target = xi * total;
   int cand = 4 * KQ;
-  int last = -1;
 #pragma unroll
   for (int q = KQ - 1; q >= 0; --q)
     if (target < P + cum[q]) cand = g * KQ + q;
-#pragma unroll
-  for (int q = 0; q < KQ; ++q)
-    if (A[q] > 0.0f) last = g * KQ + q;
   int k = quad_min_i(cand);
-  last = quad_max_i(last);
-  if (k == 4 * KQ) k = last < 0 ? 0 : last;
+  // The fallback: for xi_sel < 1 the target stays below the total, which the
+  // last lane group's running sum equals bit for bit, so only xi_sel >= 1 or
+  // a non-finite weight reaches it; evaluated when some lane of the wave
+  // needs it (the quad reduction wants every lane).
+  if (__any(k == 4 * KQ)) {
+    int last = -1;
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+      if (A[q] > 0.0f) last = g * KQ + q;
+    last = quad_max_i(last);
+    if (k == 4 * KQ) k = last < 0 ? 0 : last;
+  }
   return k;
+}
+
+// s ? a : b field by field (one select per field, no branch)
+__device__ __forceinline__ Lobe select_lobe_fields(bool s, const Lobe& a, const Lobe& b) {
+  Lobe r;
+  r.zx = s ? a.zx : b.zx;
+  r.zy = s ? a.zy : b.zy;
+  r.zz = s ? a.zz : b.zz;
+  r.xx = s ? a.xx : b.xx;
+  r.xy = s ? a.xy : b.xy;
+  r.xz = s ? a.xz : b.xz;
+  r.lam = s ? a.lam : b.lam;
+  r.a = s ? a.a : b.a;
+  r.logc = s ? a.logc : b.logc;
+  return r;
 }
 
 // The selected lobe's record, from the lane group that owns it.
@@ -158,8 +179,7 @@ __device__ __forceinline__ Lobe broadcast_lobe(const Lobe (&lb)[KQ], int k, int 
   const int gs = k / KQ, qs = k % KQ;
   Lobe mine = lb[0];
 #pragma unroll
-  for (int q = 1; q < KQ; ++q)
-    if (q == qs) mine = lb[q];
+  for (int q = 1; q < KQ; ++q) mine = select_lobe_fields(q == qs, lb[q], mine);
   const int src = gs * 16 + c;
   Lobe r;
   r.zx = __shfl(mine.zx, src);

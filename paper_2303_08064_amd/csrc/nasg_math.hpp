@@ -27,6 +27,7 @@ constexpr float kMinNormal = 1.17549435e-38f;
 
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 // e^{a - b} as a log2(e) - b log2(e) in one FMA (the second product is shared
 // across a loop over a with the same b) and one exp2
 __device__ __forceinline__ float fexp_sub(float a, float b) {
@@ -47,6 +48,42 @@ __device__ __forceinline__ float expm1f_(float x) {
   p = p * x;
   float e = fexp(x) - 1.0f;
   return fsel(fabsf(x) < 0.125f, p, e);
+}
+
+// e^x - 1 for x <= 0 (every caller but the sampler's e^{2 lam} - 1), the
+// same function with one multiply-add fewer: for -1/8 < x <= 0 the
+// polynomial x (1 + x (c0 + c1 x + c2 x^2)), whose coefficients are the
+// minimax fit of relative error on [-1/8, 0] with the linear term held at x
+// (Remez exchange; fit error 1.8e-8 relative, below FP32 rounding, where the
+// Taylor series to x^5 leaves 4.4e-8); exp(x) - 1 elsewhere.
+__device__ __forceinline__ float expm1_neg_poly(float x) {
+  float q = fmaf(x, 0.0397158824f, 0.166526049f);
+  q = fmaf(x, q, 0.499997109f);
+  return x * fmaf(x, q, 1.0f);
+}
+__device__ __forceinline__ float expm1_neg(float x) {
+  return fsel(x > -0.125f, expm1_neg_poly(x), fexp(x) - 1.0f);
+}
+
+// log(1 - w) for 0 <= w < 1/16: y (1 + y (d0 + d1 y + d2 y^2 + d3 y^3)) with
+// y = -w, the minimax fit of relative error on [-1/16, 0] with the linear
+// term held at y (Remez exchange; fit error 4e-10 relative).
+__device__ __forceinline__ float log1m_series(float w) {
+  const float y = -w;
+  float r = fmaf(y, 0.227763459f, -0.248499244f);
+  r = fmaf(y, r, 0.333364844f);
+  r = fmaf(y, r, -0.499999791f);
+  return y * fmaf(y, r, 1.0f);
+}
+
+// log1m_series(w4 / 4) from w4 = 4 w, with the same roundings: the
+// polynomial's coefficients and variable are scaled by powers of 4, which is
+// exact, so every intermediate is the same value times a power of 4.
+__device__ __forceinline__ float log1m_series4(float w4) {
+  float r = fmaf(w4, 0.227763459f * (-1.0f / 1024.0f), -0.248499244f * (1.0f / 256.0f));
+  r = fmaf(w4, r, 0.333364844f * (-1.0f / 64.0f));
+  r = fmaf(w4, r, -0.499999791f * (1.0f / 16.0f));
+  return w4 * fmaf(w4, r, -0.25f);
 }
 
 // log(1 + y) by its series to y^6 (truncation below 1e-8 relative for |y| < 1/16).
@@ -93,10 +130,17 @@ __device__ __forceinline__ void unit_pair(float c, float s, float& cu, float& su
   inv = fsel(ok, inv, 0.0f);
 }
 
+// log(2 pi) + log(one_m) - loglam - (1/2) log((1+eps)(1+eps+a)), the two
+// logarithms taken in base 2 and scaled by ln 2 together.
+__device__ __forceinline__ float log_normaliser_sum(float one_m, float loglam, float a, float eps) {
+  const float l2 = fmaf(-0.5f, flog2((1.0f + eps) * (1.0f + eps + a)), flog2(one_m));
+  return fmaf(l2, kLn2, kLog2Pi) - loglam;
+}
+
 // log K = log(2 pi) + log(1 - e^{-2 lam}) - log lam - (1/2) log((1+eps)(1+eps+a)).
 __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps) {
-  float one_m = -expm1f_(-2.0f * lam);
-  return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
+  float one_m = -expm1_neg(-2.0f * lam);
+  return log_normaliser_sum(one_m, loglam, a, eps);
 }
 
 // The same, also returning omq = 1 - q with q = 2 lam / expm1(2 lam) =
@@ -109,19 +153,14 @@ __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a
 __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a, float eps, float& omq) {
   const float x = -2.0f * lam;
   const float ex = fexp(x);                           // e^{-2 lam}
-  float p = fmaf(x, 1.0f / 120.0f, 1.0f / 24.0f);    // expm1 series, as in expm1f_
-  p = fmaf(x, p, 1.0f / 6.0f);
-  p = fmaf(x, p, 0.5f);
-  p = fmaf(x, p, 1.0f);
-  p = p * x;
-  const float one_m = -fsel(fabsf(x) < 0.125f, p, ex - 1.0f);   // 1 - e^{-2 lam}
+  const float one_m = -fsel(x > -0.125f, expm1_neg_poly(x), ex - 1.0f);   // 1 - e^{-2 lam}
   const float t = -x;
   const float t2 = t * t;
   float ser = fmaf(t2, 1.0f / 1209600.0f, -1.0f / 30240.0f);
   ser = fmaf(t2, ser, 1.0f / 720.0f);
   ser = fmaf(t2 * t2, ser, t * fmaf(t, -1.0f / 12.0f, 0.5f));
   omq = fsel(t < 0.5f, ser, 1.0f - t * ex * frcp(one_m));   // -> 1 as e^{-2 lam} underflows
-  return kLog2Pi + flog(one_m) - loglam - 0.5f * flog((1.0f + eps) * (1.0f + eps + a));
+  return log_normaliser_sum(one_m, loglam, a, eps);
 }
 
 // Raw outputs o[0..7] of one lobe -> frame, lambda, a, log K (Tab. "decoding",
@@ -135,7 +174,7 @@ __device__ __forceinline__ float log_normaliser(float lam, float loglam, float a
 // gives the tanh' factors 2 e_i/(2 - m_i)^2 and the pair's norm.
 __device__ __forceinline__ void decode_pair(float oc, float os, float& cu, float& su, float& inv_n, float& hc,
                                             float& hs) {
-  const float mc = -expm1f_(-fabsf(oc)), ms = -expm1f_(-fabsf(os));
+  const float mc = -expm1_neg(-fabsf(oc)), ms = -expm1_neg(-fabsf(os));
   const float tc = 2.0f - mc, ts = 2.0f - ms;
   const float R = frcp(tc * ts);
   float inv;
@@ -150,7 +189,7 @@ __device__ __forceinline__ void decode_pair(float oc, float os, float& cu, float
 // Gaussian / von Mises-Fisher lobe; the anisotropy output then has zero
 // gradient), 1 the NASG lobe.
 __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L, LobeAux& X, float amul = 1.0f) {
-  const float h0 = fexp(-0.5f * fabsf(o[0]));        // e^{-|o|/2}
+  const float h0 = __builtin_amdgcn_exp2f(fabsf(o[0]) * (-0.5f * kLog2e));   // e^{-|o|/2}
   const float e0 = h0 * h0;
   const float r0 = frcp(1.0f + e0);
   X.ct = copysignf((1.0f - e0) * r0, o[0]);
@@ -177,7 +216,7 @@ __device__ __forceinline__ void decode_lobe(const float o[8], float eps, Lobe& L
 // 1 - e^{-|o|}, accurate in relative terms (used where a pair of small raw
 // outputs is normalised, so their ratio must survive).
 __device__ __forceinline__ float one_minus_exp_neg(float ao) {
-  return -expm1f_(-ao);
+  return -expm1_neg(-ao);
 }
 
 // Forward-only decode for queries: the same function as decode_lobe, with
@@ -186,7 +225,7 @@ __device__ __forceinline__ float one_minus_exp_neg(float ao) {
 // log K folded into log c by the caller. Returns log K.
 __device__ __forceinline__ float decode_lobe_query(const float o[8], float eps, Lobe& L, float amul = 1.0f) {
   // theta: cos = tanh(o0/2) (absolute accuracy suffices), sin = sech(o0/2)
-  const float h0 = fexp(-0.5f * fabsf(o[0]));        // e^{-|o|/2}: sin without a square root
+  const float h0 = __builtin_amdgcn_exp2f(fabsf(o[0]) * (-0.5f * kLog2e));   // e^{-|o|/2}: sin without a square root
   const float e0 = h0 * h0;
   const float r0 = frcp(1.0f + e0);
   const float ct = copysignf((1.0f - e0) * r0, o[0]);
@@ -243,7 +282,7 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));   // u
   // log u: series of log(1 - w) near the axis, else the log of the
   // better-conditioned of 1 - w and u (one log either way)
-  float lw = log1p_series(-w);
+  float lw = log1m_series(w);
   float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
   r.L = fsel(w < 0.0625f, lw, lu);
   r.u = u;
@@ -256,10 +295,10 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   r.pm1 = fmaf(L.a, r.c2, eps);
   r.p = 1.0f + r.pm1;
   const float pl = r.p * r.L;
-  r.E = expm1f_(pl);
-  // u^p from the exponential expm1 already evaluates for |p L| >= 1/8: E + 1
+  r.E = expm1_neg(pl);                               // p L <= 0
+  // u^p from the exponential expm1 already evaluates for p L <= -1/8: E + 1
   // would round a tiny u^p to 0
-  r.epl = fsel(fabsf(pl) < 0.125f, r.E + 1.0f, fexp(pl));
+  r.epl = fsel(pl > -0.125f, r.E + 1.0f, fexp(pl));
   float lg = fmaf(2.0f * L.lam, r.E, r.pm1 * r.L);
   // G(-z) = 0: u == 0 only when v = -z exactly
   r.ell = fsel(u > 0.0f, L.logc + lg, -INFINITY);
@@ -275,16 +314,17 @@ __device__ __forceinline__ float eval_lobe_ell(const Lobe& L, float vx, float vy
   const float dx = vx - L.zx, dy = vy - L.zy, dz = vz - L.zz;
   const float sx = vx + L.zx, sy = vy + L.zy, sz = vz + L.zz;
   const float w4 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));   // 4 (1 - u)
-  const float w = 0.25f * w4;
   const float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));
-  const float lw = log1p_series(-w);
-  const float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
-  const float Lu = fsel(w < 0.0625f, lw, lu);
+  // w = w4 / 4 exactly, so the tests on w4 and 1 - w = fma(w4, -1/4, 1) are
+  // those on w, without forming it
+  const float lw = log1m_series4(w4);
+  const float lu = flog(fsel(w4 <= 2.0f, fmaf(w4, -0.25f, 1.0f), u));
+  const float Lu = fsel(w4 < 0.25f, lw, lu);
   const float X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
   const float S = w4 * u;
   const float c2 = fsel(S >= kMinNormal, fminf(X * X * frcp(S), 1.0f), 0.0f);
   const float pm1 = fmaf(L.a, c2, eps);                    // p - 1 without cancellation
-  const float lg = fmaf(2.0f * L.lam, expm1f_((1.0f + pm1) * Lu), pm1 * Lu);
+  const float lg = fmaf(2.0f * L.lam, expm1_neg((1.0f + pm1) * Lu), pm1 * Lu);
   return fsel(u > 0.0f, L.logc + lg, -INFINITY);
 }
 
@@ -340,7 +380,7 @@ __device__ __forceinline__ void sample_lobe(const Lobe& L, float xi0, float xi1,
                                             float eps, float& vx, float& vy, float& vz) {
   const float tl = 2.0f * L.lam;
   const float rtl = frcp(tl);
-  float t = expm1f_(-tl);                              // e^{-2 lam} - 1 in (-1, 0)
+  float t = expm1_neg(-tl);                            // e^{-2 lam} - 1 in (-1, 0)
   float y0 = (1.0f - xi0) * t;                         // s - 1
   float ls_near = log1pf_(y0);
   float ls_far = flog(fmaf(1.0f - xi0, fexp(-tl), xi0));
@@ -361,7 +401,7 @@ __device__ __forceinline__ void sample_lobe(const Lobe& L, float xi0, float xi1,
   float p = fmaf(L.a, cphi * cphi, 1.0f + eps);
   float Lu = lopr * frcp(p);                           // log((cos theta + 1)/2)
   float u = fexp(Lu);
-  float om = -expm1f_(Lu);                             // 1 - u
+  float om = -expm1_neg(Lu);                           // 1 - u (Lu <= 0)
   float ct = 1.0f - 2.0f * om;
   float st = 2.0f * fsqrt(fmaxf(u * om, 0.0f));
   float yx, yy, yz;
