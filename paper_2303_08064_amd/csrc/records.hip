@@ -8,23 +8,32 @@
 namespace nasg {
 
 // The record is read exactly once, so its loads are non-temporal (they do
-// not displace other data in the caches).
+// not displace other data in the caches). base: vertex v's first value in
+// its tile, rec + (v / 64) 9 K 64 + v % 64.
+template <int K>
+__device__ __forceinline__ const float* record_base(const float* __restrict__ rec, int64_t v) {
+  return rec + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
+}
+template <int K>
+__device__ __forceinline__ Lobe load_record(const float* __restrict__ base, int k) {
+  auto ld = [&](int p) { return __builtin_nontemporal_load(base + (p * K + k) * kRecTile); };
+  Lobe L;
+  L.zx = ld(0);
+  L.zy = ld(1);
+  L.zz = ld(2);
+  L.xx = ld(3);
+  L.xy = ld(4);
+  L.xz = ld(5);
+  L.lam = ld(6);
+  L.a = ld(7);
+  L.logc = ld(8);
+  return L;
+}
 template <int K>
 __device__ __forceinline__ void load_records(const float* __restrict__ rec, int64_t v, Lobe (&lb)[K]) {
-  const float* base = rec + (v / kRecTile) * 9 * K * kRecTile + (v % kRecTile);
-  auto ld = [&](int p, int k) { return __builtin_nontemporal_load(base + (p * K + k) * kRecTile); };
+  const float* base = record_base<K>(rec, v);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    lb[k].zx = ld(0, k);
-    lb[k].zy = ld(1, k);
-    lb[k].zz = ld(2, k);
-    lb[k].xx = ld(3, k);
-    lb[k].xy = ld(4, k);
-    lb[k].xz = ld(5, k);
-    lb[k].lam = ld(6, k);
-    lb[k].a = ld(7, k);
-    lb[k].logc = ld(8, k);
-  }
+  for (int k = 0; k < K; ++k) lb[k] = load_record<K>(base, k);
 }
 
 template <int K>
@@ -97,7 +106,11 @@ __global__ __launch_bounds__(256) void sample_kernel(RecArgs a) {
 
 // Mixture pdf and the gradient of log D with respect to the direction on the
 // sphere: sum_k r_k grad ell_k with r_k = D_k / D (each lobe's gradient is
-// formed in the tangent plane of v).
+// formed in the tangent plane of v). One pass over the lobes with one record
+// in registers at a time: with m the running maximum of ell_k, the sum
+// s = sum_k e^{ell_k - m} and the weighted gradient G = sum_k e^{ell_k - m}
+// grad ell_k are rescaled by e^{m_old - m} whenever m rises, so that
+// log D = m + log s and the gradient is G / s.
 template <int K>
 __global__ __launch_bounds__(256) void pdf_grad_kernel(RecArgs a) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -105,24 +118,30 @@ __global__ __launch_bounds__(256) void pdf_grad_kernel(RecArgs a) {
   float vx = a.dir[v], vy = a.dir[a.ld + v], vz = a.dir[2 * a.ld + v];
   float inv = frsq(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
   vx *= inv; vy *= inv; vz *= inv;
-  Lobe lb[K];
-  load_records<K>(a.rec, v, lb);
-  const float logq = log_mixture<K>(lb, vx, vy, vz, a.eps);
-  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-#pragma unroll
+  const float* base = record_base<K>(a.rec, v);
+  float m = -INFINITY, s = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll 2
   for (int k = 0; k < K; ++k) {
-    const Eval e = eval_lobe(lb[k], vx, vy, vz, a.eps);
-    const float r = fexp(e.ell - logq);
+    const Lobe L = load_record<K>(base, k);
+    const Eval e = eval_lobe(L, vx, vy, vz, a.eps);
     float hx, hy, hz;
-    dir_grad_lobe(lb[k], e, vx, vy, vz, hx, hy, hz);
-    gx = fmaf(r, hx, gx);
-    gy = fmaf(r, hy, gy);
-    gz = fmaf(r, hz, gz);
+    dir_grad_lobe(L, e, vx, vy, vz, hx, hy, hz);
+    const float mn = fmaxf(m, e.ell);
+    // while every term so far is e^{-inf} = 0 there is nothing to rescale
+    const bool none = mn == -INFINITY;
+    const float sc = none ? 1.0f : fexp(m - mn);
+    const float w = none ? 0.0f : fexp(e.ell - mn);
+    s = fmaf(s, sc, w);
+    gx = fmaf(gx, sc, w * hx);
+    gy = fmaf(gy, sc, w * hy);
+    gz = fmaf(gz, sc, w * hz);
+    m = mn;
   }
-  a.pdf_out[v] = fexp(logq);
-  a.grad_out[v] = gx;
-  a.grad_out[a.ld + v] = gy;
-  a.grad_out[2 * a.ld + v] = gz;
+  const float rs = frcp(s);
+  a.pdf_out[v] = m == -INFINITY ? 0.0f : fexp(m + flog(s));
+  a.grad_out[v] = gx * rs;
+  a.grad_out[a.ld + v] = gy * rs;
+  a.grad_out[2 * a.ld + v] = gz * rs;
 }
 
 template <int K>
