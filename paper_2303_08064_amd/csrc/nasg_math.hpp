@@ -8,7 +8,8 @@
 //   u = (v.z + 1)/2 = |v + z|^2 / 4,   1 - u = |v - z|^2 / 4,
 //   c^2 = (v.x)^2 / (1 - (v.z)^2) = X^2 / (X^2 + Y^2) with X = v.x, Y = v.y,
 //   log G = 2 lam (u^p - 1) + (p - 1) log u,  p = 1 + eps + a c^2,
-// with log u and u^p - 1 = expm1(p log u) taken through series near u = 1.
+// with log u and u^p - 1 = expm1(p log u) taken through minimax polynomials
+// near u = 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,7 +69,7 @@ __device__ __forceinline__ float expm1_neg(float x) {
 // log(1 - w) for 0 <= w < 1/16: y (1 + y (d0 + d1 y + d2 y^2 + d3 y^3)) with
 // y = -w, the minimax fit of relative error on [-1/16, 0] with the linear
 // term held at y (Remez exchange; fit error 4e-10 relative).
-__device__ __forceinline__ float log1m_series(float w) {
+__device__ __forceinline__ float log1m_poly(float w) {
   const float y = -w;
   float r = fmaf(y, 0.227763459f, -0.248499244f);
   r = fmaf(y, r, 0.333364844f);
@@ -76,10 +77,10 @@ __device__ __forceinline__ float log1m_series(float w) {
   return y * fmaf(y, r, 1.0f);
 }
 
-// log1m_series(w4 / 4) from w4 = 4 w, with the same roundings: the
+// log1m_poly(w4 / 4) from w4 = 4 w, with the same roundings: the
 // polynomial's coefficients and variable are scaled by powers of 4, which is
 // exact, so every intermediate is the same value times a power of 4.
-__device__ __forceinline__ float log1m_series4(float w4) {
+__device__ __forceinline__ float log1m_poly4(float w4) {
   float r = fmaf(w4, 0.227763459f * (-1.0f / 1024.0f), -0.248499244f * (1.0f / 256.0f));
   r = fmaf(w4, r, 0.333364844f * (-1.0f / 64.0f));
   r = fmaf(w4, r, -0.499999791f * (1.0f / 16.0f));
@@ -280,9 +281,9 @@ __device__ __forceinline__ Eval eval_lobe(const Lobe& L, float vx, float vy, flo
   float sx = vx + L.zx, sy = vy + L.zy, sz = vz + L.zz;
   float w = 0.25f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));   // 1 - u
   float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));   // u
-  // log u: series of log(1 - w) near the axis, else the log of the
+  // log u: a polynomial in w for log(1 - w) near the axis, else the log of the
   // better-conditioned of 1 - w and u (one log either way)
-  float lw = log1m_series(w);
+  float lw = log1m_poly(w);
   float lu = flog(fsel(w <= 0.5f, 1.0f - w, u));
   r.L = fsel(w < 0.0625f, lw, lu);
   r.u = u;
@@ -317,7 +318,7 @@ __device__ __forceinline__ float eval_lobe_ell(const Lobe& L, float vx, float vy
   const float u = 0.25f * fmaf(sx, sx, fmaf(sy, sy, sz * sz));
   // w = w4 / 4 exactly, so the tests on w4 and 1 - w = fma(w4, -1/4, 1) are
   // those on w, without forming it
-  const float lw = log1m_series4(w4);
+  const float lw = log1m_poly4(w4);
   const float lu = flog(fsel(w4 <= 2.0f, fmaf(w4, -0.25f, 1.0f), u));
   const float Lu = fsel(w4 < 0.25f, lw, lu);
   const float X = fmaf(vx, L.xx, fmaf(vy, L.xy, vz * L.xz));
