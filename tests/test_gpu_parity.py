@@ -442,6 +442,44 @@ def test_pdf_direction_gradient(name, eps):
     assert np.abs((gg * uni.T).sum(1)).max() < 1e-4 * (np.abs(gg).max() + 1)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("eps", [0.0, 0.3])
+def test_pdf_grad_rising_maximum(eps):
+    """nasg_pdf_grad keeps a running maximum of the lobes' log values and
+    rescales its sums when it rises. Here the lobes' log(A/K) climbs by 3
+    per lobe over K = 32 lobes of moderate sharpness, so the maximum rises
+    at nearly every lobe. The pdf and the gradient of log D on the sphere
+    (Sec. 3.1, eq. NASG) are compared with the oracle from the same records
+    at 1e-4, away from the lobe axes as in ``test_pdf_direction_gradient``."""
+    K, B = 32, 4099
+    rng = np.random.default_rng(31)
+    z = rng.normal(size=(B, K, 3))
+    z /= np.linalg.norm(z, axis=-1, keepdims=True)
+    t = rng.normal(size=(B, K, 3))
+    x = t - (t * z).sum(-1, keepdims=True) * z
+    x /= np.linalg.norm(x, axis=-1, keepdims=True)
+    lam = np.exp(rng.uniform(0.0, np.log(50.0), size=(B, K)))
+    a = np.exp(rng.uniform(np.log(0.1), np.log(20.0), size=(B, K)))
+    logc = 3.0 * np.arange(K)[None, :] - 90.0 + rng.uniform(-1.0, 1.0, size=(B, K))
+    bk9 = np.concatenate([z, x, lam[..., None], a[..., None], logc[..., None]], -1)
+    g, _ = make_guide("c5_bf16", eps=eps, max_batch=B)       # the record kernels need only K and eps
+    uni = np.ascontiguousarray(synth.unit_vectors(B, synth.rng_for(32)).T.astype(np.float32))
+    pdf, grad = g.pdf_grad(to_dev(bk9_to_rec(bk9, K)), to_dev(uni))
+    g.close()
+    rec64 = rec_to_bk9(torch.tensor(bk9_to_rec(bk9, K)), B, K)   # the float32 records the GPU read
+    lob = onasg.lobes_from_record(rec64, eps)
+    v = torch.tensor(uni.T.astype(np.float64))
+    lq = onasg.mixture_log_pdf(v, lob).numpy()
+    gr = onasg.log_pdf_direction_grad(v, lob).numpy()
+    gg = grad.cpu().numpy().T.astype(np.float64)
+    vz = (v[:, None, :] * lob.z).sum(-1).numpy()
+    ok = ~((np.abs(vz) > np.cos(5e-2)).any(-1))
+    assert ok.mean() > 0.5
+    assert np.abs(np.log(pdf.cpu().numpy().astype(np.float64)) - lq)[ok].max() < 1e-4
+    err = np.linalg.norm(gg - gr, axis=1) / (np.linalg.norm(gr, axis=1) + 1.0)
+    assert err[ok].max() < 1e-4, err[ok].max()
+
+
 # ---- isotropic lobes (a = 0: the spherical-Gaussian comparison model) ----
 
 @pytest.mark.parametrize("name", ["c2_f32", "c3_bf16"])
