@@ -215,15 +215,16 @@ __device__ __forceinline__ void wgrad_tiles(const S* dst, const S* hst, const in
 
 // Ownership of a layer's dW tiles (RT row tiles x CT column tiles) among the
 // NW waves of a workgroup, tile j of a wave being (rt(w, j), ct(w, j)):
-// * RT >= NW (row mode): wave w owns row tiles w, w + NW, ... and every
-//   column tile (per staged block: CT column operands, one row operand per
-//   row tile);
-// * RT < NW (column mode, NW a multiple of CT): wave w owns column tile
+// * RT a multiple of NW (row mode): wave w owns row tiles w, w + NW, ... and
+//   every column tile (per staged block: CT column operands, one row operand
+//   per row tile);
+// * otherwise (column mode, NW a multiple of CT): wave w owns column tile
 //   w % CT and row tiles w / CT + (NW / CT) j below RT (one column operand,
-//   one row operand per tile).
+//   one row operand per tile), so that an odd row tile (the selection
+//   output's) adds one tile to some waves rather than CT to one.
 template <int RT, int CT, int NW>
 struct Own {
-  static constexpr bool ROW = RT >= NW;
+  static constexpr bool ROW = RT >= NW && RT % NW == 0;
   static_assert(ROW || NW % CT == 0, "waves must split evenly over the column tiles");
   static constexpr int STEP = ROW ? NW : NW / CT;
   static constexpr int NRW = (RT + STEP - 1) / STEP;        // row tiles per wave
