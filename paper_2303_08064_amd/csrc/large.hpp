@@ -624,7 +624,10 @@ __global__ __launch_bounds__(256) void gradout_kernel(LargeTrainArgs a) {
 // next tile's layer 0 resident.
 constexpr int kBwdWaves = 8;
 constexpr int kBwdV = 16 * kBwdWaves;   // vertices per backward tile
-constexpr int kBwdSP = kBwdV + 8;       // staging pitch (bf16)
+// staging pitch (bf16): 144 values are 18 16-byte units, which makes the
+// weight-gradient operand reads free of LDS bank conflicts (units per row
+// 2 mod 4; 136 costs ~3 conflict cycles per 16-byte read on gfx950)
+constexpr int kBwdSP = kBwdV + 16;
 
 // LDS of the weight buffers, and of the backward kernels (weights + staging)
 template <int H, int K, int PREC, int SEL, int ENC>

@@ -38,7 +38,14 @@ struct TrainCfg {
   static constexpr int NW = train_waves<PREC>();
   static constexpr int NV = 16 * NW;            // vertices per tile
   static constexpr int RMAX = (16 * MTO > H) ? 16 * MTO : H;   // rows of the largest delta
-  static constexpr int SP = PREC == 1 ? NV + 8 : NV + 4;   // staging pitch (elements)
+  // staging pitch (elements). BF16: a row of NV + 16 = 144 values is 18
+  // 16-byte units; the weight-gradient operand reads (lane (g, c): 16 B of
+  // row c at unit g) are free of LDS bank conflicts when the row's units are
+  // 2 mod 4 (measured on gfx950: 136, 152, 160, 168 and 184 values per row
+  // each cost ~3 conflict cycles per read, 144 and 176 none). The selection
+  // networks' staging at 144 would exceed the LDS beside their weights, so
+  // they keep 136. FP32 reads one value per lane, conflict-free at NV + 4.
+  static constexpr int SP = PREC == 1 ? (SEL == 1 ? NV + 8 : NV + 16) : NV + 4;
   typedef Own<MTH, 1, NW> O0;                   // layer 0
   typedef Own<MTH, CTH, NW> OH;                 // hidden layers
   typedef Own<MTO, CTH, NW> OO;                 // output layer
